@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Throughput of multiscale sphere tracing with analytic normals on one MI355X.
+
+Workload (default): the three-level nested SIREN stack (32,1) |> (64,1) |>
+(256,2) rendered at 1920x1080, every ray traced to a hit or a miss and every hit
+given its analytic unit normal.  One step = one trace_rays call over the whole
+frame with rays already resident in device memory.  Measured forms: FP32 and
+BF16 hidden layers (the headline value is the --precision form).
+
+Prints progress on stderr and ONE JSON line on stdout with the rays/s, the
+roofline of the dominant kernel (HIP events around each launch, algorithmic
+hidden-layer FLOPs from the per-level step counts), the error statistics
+against the FP64 CPU oracle on a row sample, and the oracle's own rate on that
+sample (cpu_baseline).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "rays/s to hit+normal at 1080p, 3-level SIREN; FP32 vs BF16-MFMA at stated err"
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}  # dense MFMA, MI355X
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def hidden_flops(net) -> int:
+    """2 FLOP per multiply-accumulate of the width x width layers of one forward."""
+    return 2 * (net.n_sine - 1) * net.width * net.width
+
+
+def normal_hidden_flops(net) -> int:
+    """Forward plus three tangent columns through the hidden layers."""
+    return 4 * hidden_flops(net)
+
+
+def run_form(scene, precision, o, v, t, steps, warmup):
+    import torch
+    import paper_2201_09147_amd as nnm
+    dev = torch.device("cuda", 0)
+    n = o.shape[0]
+    stack = nnm.load_siren_stack(scene, precision, 0)
+    out = {
+        "depth": torch.empty(n, dtype=torch.float32, device=dev),
+        "hit": torch.empty(n, dtype=torch.uint8, device=dev),
+        "normal": torch.empty((n, 3), dtype=torch.float32, device=dev),
+        "steps": torch.empty((n, stack.m), dtype=torch.uint8, device=dev),
+        "status": torch.empty(n, dtype=torch.uint8, device=dev),
+    }
+    prof = nnm.Profiler()
+    params = nnm.TraceParams(scene.step_scale, scene.eps, scene.far, scene.max_steps)
+
+    def call(p):
+        nnm.trace_rays(stack, p, o, v, t, out["depth"], out["hit"], out["normal"], out["steps"],
+                       out["status"])
+
+    for _ in range(warmup):
+        call(params)
+    torch.cuda.synchronize()
+    log(f"[{precision}] warmup done ({warmup} steps)")
+    timed = nnm.TraceParams(scene.step_scale, scene.eps, scene.far, scene.max_steps, profiler=prof)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        call(timed)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / steps
+    report = prof.report()
+    log(f"[{precision}] {steps} steps: {ms:.3f} ms/step, {n / ms * 1e3 / 1e9:.3f} Grays/s")
+    evals = out["steps"].to(torch.int64).sum(dim=0).cpu().tolist()
+    hits = int(out["hit"].to(torch.int64).sum().item())
+    kernels = []
+    for e in report:
+        lvl = scene.levels[e["level"]]
+        if e["kind"] == "trace":
+            flops = evals[e["level"]] * hidden_flops(lvl.net)
+            units = evals[e["level"]]
+        else:
+            flops = hits * normal_hidden_flops(lvl.net)
+            units = hits
+        avg_ms = e["total_ms"] / max(e["launches"], 1)
+        kernels.append({"kind": e["kind"], "level": e["level"], "width": e["width"], "avg_ms": avg_ms,
+                        "evals": units, "hidden_flops": flops,
+                        "tflops": flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0})
+    res = {"precision": precision, "ms_per_step": ms, "rays_per_s": n / (ms * 1e-3), "hits": hits,
+           "evals_per_level": evals, "kernels": kernels,
+           "outputs": {k: v_.cpu().numpy() for k, v_ in out.items()}}
+    prof.close()
+    stack.close()
+    return res
+
+
+def roofline(form):
+    dom = max(form["kernels"], key=lambda k: k["avg_ms"])
+    peak = PEAK_TFLOPS[form["precision"]]
+    return {"bound": "mfma", "achieved": round(dom["tflops"], 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(dom["tflops"] / peak, 5), "traffic": None,
+            "kernel": f"k_trace_level<{dom['width']}> level {dom['level']}" if dom["kind"] == "trace"
+            else f"k_normal<{dom['width']}>",
+            "avg_ms": round(dom["avg_ms"], 4), "flops_per_launch": dom["hidden_flops"]}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="stack3_1080p")
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--forms", default="fp32,bf16")
+    ap.add_argument("--cpu-rows-every", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): rays are independent, so a "
+              f"frame shards across GPUs without communication; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import nnm_inputs as ni
+
+    scene = ni.make_scene(args.workload)
+    o_np, v_np, t_np = scene.rays()
+    dev = torch.device("cuda", 0)
+    o = torch.from_numpy(o_np).to(dev)
+    v = torch.from_numpy(v_np).to(dev)
+    t = torch.from_numpy(t_np).to(dev) if t_np is not None else None
+    n = o_np.shape[0]
+    log(f"workload {args.workload}: {n} rays, levels "
+        + " |> ".join(f"({l.net.width},{l.net.n_sine - 1})" for l in scene.levels))
+
+    forms = [f for f in args.forms.split(",") if f]
+    if args.precision not in forms:
+        forms.append(args.precision)
+    results = {f: run_form(scene, f, o, v, t, args.steps, args.warmup) for f in forms}
+
+    cpu = None
+    errors = {}
+    if not args.no_cpu_baseline:
+        from oracle import tracing as orc
+        rows = np.arange(0, scene.height, args.cpu_rows_every)
+        idx = (rows[:, None] * scene.width + np.arange(scene.width)[None, :]).reshape(-1)
+        threads = orc.max_threads()
+        log(f"oracle on {idx.size} rays (every {args.cpu_rows_every}th row), {threads} threads")
+        c0 = time.perf_counter()
+        ref = orc.trace(scene, o_np[idx], v_np[idx], None if t_np is None else t_np[idx])
+        c1 = time.perf_counter()
+        cpu = {"value": round(idx.size / (c1 - c0), 1), "unit": "rays/s", "cores": threads, "kind": "oracle",
+               "sample": f"every {args.cpu_rows_every}th row of the {scene.width}x{scene.height} frame "
+                         f"({idx.size} rays), FP64, {c1 - c0:.1f} s"}
+        log(f"oracle: {cpu['value']} rays/s")
+        for f, r in results.items():
+            g = {k: val[idx] for k, val in r["outputs"].items()}
+            hit, rhit = g["hit"] == 1, ref["hit"] == 1
+            both = hit & rhit
+            a64, b64 = g["normal"][both].astype(np.float64), ref["normal"][both]
+            ang = np.degrees(np.arctan2(np.linalg.norm(np.cross(a64, b64), axis=1), np.sum(a64 * b64, axis=1)))
+            errors[f] = {"mask_agreement": round(float(np.mean(hit == rhit)), 6),
+                         "depth_max_abs_err": float(np.abs(g["depth"][both] - ref["depth"][both]).max()),
+                         "normal_angle_mean_deg": float(ang.mean()),
+                         "normal_angle_max_deg": float(ang.max()),
+                         "common_hits": int(both.sum())}
+            log(f"[{f}] vs oracle: {errors[f]}")
+
+    head = results[args.precision]
+    line = {
+        "metric": METRIC,
+        "value": round(head["rays_per_s"], 1),
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "rays": n, "width": scene.width, "height": scene.height,
+                   "levels": [f"({l.net.width},{l.net.n_sine - 1})" for l in scene.levels],
+                   "deltas": [l.delta for l in scene.levels[:-1]], "eps": scene.eps,
+                   "step_scale": scene.step_scale, "max_steps_per_level": scene.max_steps},
+        "roofline": roofline(head),
+        "cpu_baseline": cpu,
+        "errors_vs_oracle": errors,
+        "forms": {f: {"rays_per_s": round(r["rays_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                      "roofline": roofline(r), "hits": r["hits"], "evals_per_level": r["evals_per_level"],
+                      "frame_mfma_frac": round(sum(k["hidden_flops"] for k in r["kernels"])
+                                               / (r["ms_per_step"] * 1e-3) / 1e12
+                                               / PEAK_TFLOPS[r["precision"]], 5),
+                      "kernels": [{k2: (round(v2, 5) if isinstance(v2, float) else v2) for k2, v2 in k.items()}
+                                  for k in r["kernels"]]}
+                  for f, r in results.items()},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

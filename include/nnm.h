@@ -1,0 +1,215 @@
+/*
+ * nnm.h -- C ABI of libnnm: sphere tracing of nested sinusoidal-MLP (SIREN)
+ * signed distance functions on AMD Instinct MI355X (gfx950), after da Silva et
+ * al., "Neural Implicit Mapping via Nested Neighborhoods".
+ *
+ * Conventions for every entry point:
+ *   - Return value: NNM_OK (0) or a negative NNM_E_* code; nnm_last_error()
+ *     returns a thread-local message for the last failure.  Argument and
+ *     descriptor validation happens before anything is enqueued, so a failed
+ *     call never writes partial output.
+ *   - Arrays named "device" are caller-owned device memory on the stack's
+ *     device; the library never frees them.  Arrays named "host" are read
+ *     during the call only.
+ *   - Calls that take a stream (a hipStream_t passed as void*; NULL is the
+ *     null stream) are asynchronous on that stream.  Device faults surface on a
+ *     later call or on nnm_sync().
+ *   - n == 0 is a no-op returning NNM_OK.
+ *   - Levels are 0-based.  Points and directions are [n][3] float32 row major.
+ */
+#ifndef NNM_H
+#define NNM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define NNM_OK 0
+#define NNM_E_INVAL (-1)       /* null pointer, bad level, n < 0, bad parameter */
+#define NNM_E_FORMAT (-2)      /* malformed network file or descriptor shape */
+#define NNM_E_NONFINITE (-3)   /* NaN or Inf in weights, amplitudes or deltas */
+#define NNM_E_LIPSCHITZ (-4)   /* Lipschitz bound of a level exceeds lipschitz_max */
+#define NNM_E_NESTING (-5)     /* deltas not strictly decreasing and positive */
+#define NNM_E_NOMEM (-6)       /* host or device allocation failed */
+#define NNM_E_DEVICE (-7)      /* HIP runtime error (launch, copy, fault) */
+#define NNM_E_UNSUPPORTED (-8) /* width / input size / precision not built */
+#define NNM_E_IO (-9)          /* file could not be read */
+
+/* Precision of the hidden (width x width) layers.  The first layer, the sine
+   argument reduction, the biases, the output layer and the scene terms always
+   run in float32; products accumulate in float32. */
+#define NNM_PREC_FP32 0
+#define NNM_PREC_BF16 1
+#define NNM_PREC_FP16 2
+
+/* Per-ray status bits written by trace_rays. */
+#define NNM_ST_HIT 1        /* the last traced level reached d <= eps */
+#define NNM_ST_FAR 2        /* the ray parameter passed far: a miss */
+#define NNM_ST_BUDGET 4     /* a level used max_steps evaluations: a miss */
+#define NNM_ST_NEG_STEP 8   /* some step had d < 0 (start inside a band) */
+#define NNM_ST_NONFINITE 16 /* a non-finite scene value: a miss */
+
+/* ------------------------------------------------------------ descriptors */
+
+/* One network of the nested sequence with its scene terms (Sec. 3.2, Eq.(1)):
+     f_j(x, t) = [|x - c(t)| - r0] + amplitude * N_j(input)
+   with input = x, x - c(t) (follow_center) or (x, t) for d_in == 4, and N_j the
+   MLP of Eq.(2), N(p) = W_K h_K + b_K, h_0 = p, h_{i+1} = sin(W_i h_i + b_i).
+   params: host float32, W_0, b_0, W_1, b_1, ..., W_K, b_K, each W_i row major
+   [out][in]; shapes [width][d_in], [width][width] (K - 1 times), [1][width].
+   omega0 of the SIREN first layer must already be folded into W_0, b_0. */
+typedef struct {
+  int32_t d_in;          /* 3 (x, y, z) or 4 (x, y, z, t) */
+  int32_t width;         /* 32, 64, 128 or 256 */
+  int32_t n_sine;        /* K sine layers (1 .. 8) */
+  int32_t follow_center; /* 1: the net input is x - c(t) */
+  float amplitude;       /* scale of the network term (finite) */
+  float delta;           /* threshold delta_j of the nesting condition; ignored
+                            on the last level of the sequence */
+  const float* params;   /* host, see above */
+} nnm_level_desc;
+
+/* A nested sequence f_1 |> ... |> f_m (Sec. 3.2) and its common base term. */
+typedef struct {
+  int32_t n_levels;      /* m, 1 .. 8 */
+  int32_t base_sphere;   /* 1: include |x - c(t)| - r0 in every f_j */
+  float r0;              /* sphere radius */
+  float rho;             /* c(t) = rho (cos 2 pi t, sin 2 pi t, 0); 0: static */
+  float lipschitz_max;   /* reject a level whose bound 1 + a * prod_i sigma(W_i)
+                            (spatial columns of W_0; 0 + ... without the sphere)
+                            exceeds this; 0 disables the check */
+  int32_t reserved;
+  const nnm_level_desc* levels; /* host, n_levels entries */
+} nnm_stack_desc;
+
+typedef struct nnm_stack nnm_stack; /* opaque; immutable after loading */
+
+/* Multiscale sphere tracing parameters (Algorithm 1, Sec. 4).  Per level j the
+   tracer repeats: d = f_j(o + tau v) - delta_j (delta = 0 on final_level);
+   tau += step_scale * d; then tau > far -> miss; d <= eps -> next level;
+   max_steps evaluations used -> miss. */
+typedef struct nnm_profiler nnm_profiler; /* see "profiling" below */
+
+typedef struct {
+  float step_scale;      /* s, in (0, 1] */
+  float eps;             /* eps > 0 */
+  float far;             /* far > 0 */
+  int32_t max_steps;     /* evaluations per level, 1 .. 255 */
+  int32_t final_level;   /* last traced level (m - 1: full; m - 2: NNM) */
+  int32_t normal_level;  /* level whose unit gradient is returned as the normal;
+                            > final_level is neural normal mapping (Sec. 5) */
+  int32_t mode;          /* 0: eps-terminated (the only mode) */
+  int32_t reserved;
+  nnm_profiler* profiler; /* NULL, or a profiler that times every kernel of the call */
+} nnm_trace_params;
+
+/* ---------------------------------------------------------------- stacks */
+
+/* Validates a stack descriptor on the host only (no device use): shapes and
+   supported sizes (NNM_E_UNSUPPORTED / NNM_E_FORMAT), finiteness
+   (NNM_E_NONFINITE), deltas of levels 0 .. m-2 strictly decreasing and > 0
+   (NNM_E_NESTING) and the Lipschitz bound (NNM_E_LIPSCHITZ). */
+int nnm_validate_stack(const nnm_stack_desc* desc, int precision);
+
+/* The Lipschitz product bound of one level (power iteration in float64 on the
+   host): amplitude * sigma(W_0[:, 0:3]) * prod_{i>=1} sigma(W_i), plus 1 when
+   base_sphere.  Returns NNM_OK and writes *bound. */
+int nnm_level_lipschitz_bound(const nnm_level_desc* level, int base_sphere, double* bound);
+
+/* Validates desc, packs the weights for `precision` and uploads them to
+   `device`.  The descriptor may be freed afterwards.  *out is owned by the
+   caller and released with free_siren_stack. */
+int load_siren_stack(const nnm_stack_desc* desc, int precision, int device, nnm_stack** out);
+
+/* Frees the library-owned device copies of a stack; NULL is a no-op. */
+void free_siren_stack(nnm_stack* stack);
+
+/* Number of levels and precision of a loaded stack (NULL -> -1). */
+int nnm_stack_levels(const nnm_stack* stack);
+int nnm_stack_precision(const nnm_stack* stack);
+
+/* ---------------------------------------------------------------- tracing */
+
+/* Multiscale sphere tracing of n rays (Algorithm 1) with the analytic normal of
+   level normal_level at the end point (Sec. 5.1; neural normal mapping when
+   normal_level > final_level, Sec. 5).
+     o, v    device [n][3] float32; v of unit length
+     t       device [n] float32 times, or NULL (t = 0)
+     depth   device [n] float32 out: ray parameter tau of the end point; +inf on a miss
+     hit     device [n] uint8 out: 1 hit, 0 miss
+     normal  device [n][3] float32 out: unit grad f_normal_level at o + tau v
+             (0 on a miss), or NULL to skip the normal pass
+     steps   device [n][m] uint8 out: evaluations per level (0 for levels not
+             reached), or NULL
+     status  device [n] uint8 out: NNM_ST_* bits, or NULL
+   Uses stream-ordered scratch (ray queues and counters) of about 9 n bytes. */
+int trace_rays(const nnm_stack* stack, const nnm_trace_params* params, int64_t n, const float* o,
+               const float* v, const float* t, float* depth, uint8_t* hit, float* normal,
+               uint8_t* steps, uint8_t* status, void* stream);
+
+/* Analytic gradient of one scene function (Eq.(3)-(4) with the G_i form of
+   Alg. 2, one shared forward for the three tangent columns):
+     x      device [n][3] points; t device [n] or NULL
+     value  device [n] out: f_level(x, t), or NULL
+     grad   device [n][3] out: raw grad_x f_level (not normalised) */
+int analytic_normal(const nnm_stack* stack, int level, int64_t n, const float* x, const float* t,
+                    float* value, float* grad, void* stream);
+
+/* The raw network N_level and its spatial gradient (no scene terms, no
+   amplitude): value device [n] (or NULL), grad device [n][3] (or NULL). */
+int nnm_net_eval(const nnm_stack* stack, int level, int64_t n, const float* x, const float* t,
+                 float* value, float* grad, void* stream);
+
+/* -------------------------------------------------------------- profiling */
+
+/* A profiler records a HIP event pair around every kernel that trace_rays
+   launches while it is attached to the trace parameters (events on the call's
+   stream; no synchronisation until a report is requested).  Entries are keyed
+   by (kind, level): kind 0 = tracing of one level, 1 = normal pass. */
+#define NNM_PROF_MAX 32
+typedef struct {
+  int32_t n_entries;
+  int32_t kind[NNM_PROF_MAX];
+  int32_t level[NNM_PROF_MAX];
+  int32_t width[NNM_PROF_MAX];
+  int64_t launches[NNM_PROF_MAX];
+  double total_ms[NNM_PROF_MAX];
+} nnm_profile_report;
+
+int nnm_profiler_create(nnm_profiler** out);
+void nnm_profiler_free(nnm_profiler* prof);
+/* Discards recorded events. */
+int nnm_profiler_reset(nnm_profiler* prof);
+/* Synchronises the recorded events and sums their durations per entry. */
+int nnm_profiler_report(nnm_profiler* prof, nnm_profile_report* out);
+
+/* --------------------------------------------------------------- utilities */
+
+/* Network file: "NNMW", u32 version 1, u32 d_in, u32 width, u32 n_sine,
+   3 x u32 reserved, then the float32 parameters in nnm_level_desc order.
+   On success *params_out is malloc'ed (free with nnm_free) and the shape
+   fields are written.  Errors: NNM_E_IO, NNM_E_FORMAT. */
+int nnm_read_net_file(const char* path, int32_t* d_in, int32_t* width, int32_t* n_sine,
+                      float** params_out, int64_t* n_params);
+void nnm_free(void* p);
+
+/* Number of float32 parameters of a network shape (< 0 if unsupported). */
+int64_t nnm_param_count(int32_t d_in, int32_t width, int32_t n_sine);
+
+/* Blocks until `stream` is idle and reports a pending device error. */
+int nnm_sync(void* stream);
+
+/* Thread-local description of the last error ("" if none). */
+const char* nnm_last_error(void);
+
+/* Library version string. */
+const char* nnm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNM_H */

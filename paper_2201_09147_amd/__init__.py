@@ -1,0 +1,40 @@
+"""Python binding of libnnm: sphere tracing of nested SIREN SDFs on MI355X.
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libnnm.so`` (built by ``paper_2201_09147_amd.build``).  Importing works without
+the library; the first call into it raises ``NnmError`` if it is not built.
+Device arrays are torch tensors on the stack's device; streams are torch
+streams (default: the current stream).
+
+Entry points (same names as the C ABI in include/nnm.h):
+  load_siren_stack, free_siren_stack, trace_rays, analytic_normal,
+  nnm_net_eval, nnm_validate_stack, nnm_read_net_file, nnm_sync
+plus ``render`` (allocates outputs and calls trace_rays).
+"""
+
+from ._binding import (  # noqa: F401
+    NnmError,
+    LevelSpec,
+    Stack,
+    TraceParams,
+    Profiler,
+    PRECISIONS,
+    ST_HIT,
+    ST_FAR,
+    ST_BUDGET,
+    ST_NEG_STEP,
+    ST_NONFINITE,
+    library_path,
+    load_library,
+    load_siren_stack,
+    free_siren_stack,
+    trace_rays,
+    analytic_normal,
+    nnm_net_eval,
+    nnm_validate_stack,
+    nnm_level_lipschitz_bound,
+    nnm_read_net_file,
+    nnm_sync,
+    render,
+    levels_from_scene,
+)

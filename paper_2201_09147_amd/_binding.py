@@ -1,0 +1,375 @@
+"""ctypes marshalling of libnnm's C ABI (include/nnm.h).  No computation here."""
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_float, c_int, c_int32, c_int64, c_void_p
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libnnm.so")
+
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+ST_HIT, ST_FAR, ST_BUDGET, ST_NEG_STEP, ST_NONFINITE = 1, 2, 4, 8, 16
+_ERRORS = {-1: "E_INVAL", -2: "E_FORMAT", -3: "E_NONFINITE", -4: "E_LIPSCHITZ", -5: "E_NESTING",
+           -6: "E_NOMEM", -7: "E_DEVICE", -8: "E_UNSUPPORTED", -9: "E_IO"}
+
+
+class NnmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _LevelDesc(ctypes.Structure):
+    _fields_ = [("d_in", c_int32), ("width", c_int32), ("n_sine", c_int32), ("follow_center", c_int32),
+                ("amplitude", c_float), ("delta", c_float), ("params", POINTER(c_float))]
+
+
+class _StackDesc(ctypes.Structure):
+    _fields_ = [("n_levels", c_int32), ("base_sphere", c_int32), ("r0", c_float), ("rho", c_float),
+                ("lipschitz_max", c_float), ("reserved", c_int32), ("levels", POINTER(_LevelDesc))]
+
+
+class _TraceParams(ctypes.Structure):
+    _fields_ = [("step_scale", c_float), ("eps", c_float), ("far", c_float), ("max_steps", c_int32),
+                ("final_level", c_int32), ("normal_level", c_int32), ("mode", c_int32),
+                ("reserved", c_int32), ("profiler", c_void_p)]
+
+
+_PROF_MAX = 32
+
+
+class _ProfileReport(ctypes.Structure):
+    _fields_ = [("n_entries", c_int32), ("kind", c_int32 * _PROF_MAX), ("level", c_int32 * _PROF_MAX),
+                ("width", c_int32 * _PROF_MAX), ("launches", c_int64 * _PROF_MAX),
+                ("total_ms", c_double * _PROF_MAX)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libnnm.so (raises NnmError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise NnmError(-7, f"{_LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = c_void_p
+    sig = {
+        "nnm_validate_stack": ([P, c_int], c_int),
+        "nnm_level_lipschitz_bound": ([P, c_int, P], c_int),
+        "load_siren_stack": ([P, c_int, c_int, P], c_int),
+        "free_siren_stack": ([P], None),
+        "nnm_stack_levels": ([P], c_int),
+        "nnm_stack_precision": ([P], c_int),
+        "trace_rays": ([P, P, c_int64, P, P, P, P, P, P, P, P, P], c_int),
+        "analytic_normal": ([P, c_int, c_int64, P, P, P, P, P], c_int),
+        "nnm_net_eval": ([P, c_int, c_int64, P, P, P, P, P], c_int),
+        "nnm_read_net_file": ([ctypes.c_char_p, P, P, P, P, P], c_int),
+        "nnm_free": ([P], None),
+        "nnm_param_count": ([c_int32, c_int32, c_int32], c_int64),
+        "nnm_sync": ([P], c_int),
+        "nnm_last_error": ([], ctypes.c_char_p),
+        "nnm_version": ([], ctypes.c_char_p),
+        "nnm_profiler_create": ([P], c_int),
+        "nnm_profiler_free": ([P], None),
+        "nnm_profiler_reset": ([P], c_int),
+        "nnm_profiler_report": ([P, P], c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = load_library().nnm_last_error().decode(errors="replace")
+        raise NnmError(rc, msg)
+
+
+# ------------------------------------------------------------------ descriptors
+
+@dataclass
+class LevelSpec:
+    """One level: network shape, float32 parameters (file order), scene terms."""
+    d_in: int
+    width: int
+    n_sine: int
+    params: np.ndarray
+    amplitude: float
+    delta: float = 0.0
+    follow_center: bool = False
+
+
+def levels_from_scene(scene) -> List[LevelSpec]:
+    """LevelSpecs of an ``nnm_inputs`` scene (duck-typed: level.net, .amplitude, ...)."""
+    out = []
+    for l in scene.levels:
+        out.append(LevelSpec(l.net.d_in, l.net.width, l.net.n_sine,
+                             np.ascontiguousarray(l.net.flat(), dtype=np.float32),
+                             float(l.amplitude), float(l.delta), bool(l.follow_center)))
+    return out
+
+
+class _Desc:
+    """Keeps parameter arrays alive while the C descriptor is in use."""
+
+    def __init__(self, levels: List[LevelSpec], base_sphere: bool, r0: float, rho: float,
+                 lipschitz_max: float):
+        self.params = [np.ascontiguousarray(l.params, dtype=np.float32) for l in levels]
+        arr = (_LevelDesc * max(len(levels), 1))()
+        for j, l in enumerate(levels):
+            arr[j].d_in = int(l.d_in)
+            arr[j].width = int(l.width)
+            arr[j].n_sine = int(l.n_sine)
+            arr[j].follow_center = 1 if l.follow_center else 0
+            arr[j].amplitude = float(l.amplitude)
+            arr[j].delta = float(l.delta)
+            arr[j].params = self.params[j].ctypes.data_as(POINTER(c_float))
+        self.arr = arr
+        self.desc = _StackDesc(len(levels), 1 if base_sphere else 0, float(r0), float(rho),
+                               float(lipschitz_max), 0, ctypes.cast(arr, POINTER(_LevelDesc)))
+
+    def ptr(self):
+        return ctypes.cast(ctypes.byref(self.desc), c_void_p)
+
+
+def _prec(precision) -> int:
+    if isinstance(precision, str):
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {list(PRECISIONS)}")
+        return PRECISIONS[precision]
+    return int(precision)
+
+
+def nnm_validate_stack(levels: List[LevelSpec], precision="fp32", base_sphere=True, r0=0.6, rho=0.0,
+                       lipschitz_max=1.03) -> int:
+    """Host-only validation; returns the C return code (0 = valid)."""
+    d = _Desc(levels, base_sphere, r0, rho, lipschitz_max)
+    return load_library().nnm_validate_stack(d.ptr(), _prec(precision))
+
+
+def nnm_level_lipschitz_bound(level: LevelSpec, base_sphere=True) -> float:
+    d = _Desc([level], base_sphere, 0.6, 0.0, 0.0)
+    out = c_double()
+    _check(load_library().nnm_level_lipschitz_bound(ctypes.cast(d.arr, c_void_p), 1 if base_sphere else 0,
+                                                    ctypes.cast(ctypes.byref(out), c_void_p)))
+    return out.value
+
+
+class Stack:
+    """A loaded (immutable) nested sequence of networks on one device."""
+
+    def __init__(self, handle, m: int, precision: int, device: int):
+        self._h = handle
+        self.m = m
+        self.precision = precision
+        self.device = device
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise NnmError(-1, "stack has been freed")
+        return self._h
+
+    def close(self):
+        if self._h:
+            load_library().free_siren_stack(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def load_siren_stack(levels, precision="fp32", device: int = 0, base_sphere=True, r0=0.6, rho=0.0,
+                     lipschitz_max=1.03) -> Stack:
+    """Validate, pack and upload a nested sequence (list of LevelSpec or a scene)."""
+    if not isinstance(levels, (list, tuple)):
+        scene = levels
+        levels = levels_from_scene(scene)
+        base_sphere, r0, rho = scene.base_sphere, scene.r0, scene.rho
+    d = _Desc(list(levels), base_sphere, r0, rho, lipschitz_max)
+    h = c_void_p()
+    p = _prec(precision)
+    _check(load_library().load_siren_stack(d.ptr(), p, int(device), ctypes.cast(ctypes.byref(h), c_void_p)))
+    return Stack(h, len(levels), p, int(device))
+
+
+def free_siren_stack(stack: Stack):
+    stack.close()
+
+
+class Profiler:
+    """HIP-event timing of every kernel launched by trace_rays while attached."""
+
+    def __init__(self):
+        h = c_void_p()
+        _check(load_library().nnm_profiler_create(ctypes.cast(ctypes.byref(h), c_void_p)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def reset(self):
+        _check(load_library().nnm_profiler_reset(self._h))
+
+    def report(self):
+        """List of dicts (kind 'trace'/'normal', level, width, launches, total_ms)."""
+        r = _ProfileReport()
+        _check(load_library().nnm_profiler_report(self._h, ctypes.cast(ctypes.byref(r), c_void_p)))
+        return [{"kind": ("trace", "normal")[r.kind[i]], "level": r.level[i], "width": r.width[i],
+                 "launches": int(r.launches[i]), "total_ms": float(r.total_ms[i])}
+                for i in range(r.n_entries)]
+
+    def close(self):
+        if self._h:
+            load_library().nnm_profiler_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class TraceParams:
+    step_scale: float = 0.9
+    eps: float = 1e-4
+    far: float = 5.0
+    max_steps: int = 64
+    final_level: int = -1    # -1: last level
+    normal_level: int = -1   # -1: final_level
+    mode: int = 0
+    profiler: Optional[Profiler] = None
+
+    def c(self, m: int) -> _TraceParams:
+        fl = m - 1 if self.final_level < 0 else self.final_level
+        nl = fl if self.normal_level < 0 else self.normal_level
+        prof = self.profiler.handle if self.profiler is not None else None
+        return _TraceParams(self.step_scale, self.eps, self.far, self.max_steps, fl, nl, self.mode, 0, prof)
+
+
+def _dev_ptr(t, dtype, shape, name, device, allow_none=True):
+    """Validate a torch tensor argument and return its device pointer (marshalling only)."""
+    if t is None:
+        if allow_none:
+            return None
+        raise NnmError(-1, f"{name} is required")
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise NnmError(-1, f"{name} must be a torch tensor")
+    if t.device.type != "cuda" or (t.device.index if t.device.index is not None else 0) != device:
+        raise NnmError(-1, f"{name} must live on cuda:{device}")
+    if t.dtype != dtype:
+        raise NnmError(-1, f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise NnmError(-1, f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise NnmError(-1, f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return c_void_p(t.data_ptr()) if t.numel() else c_void_p(0)
+
+
+def _stream_ptr(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return c_void_p(stream.cuda_stream)
+
+
+def trace_rays(stack: Stack, params: TraceParams, o, v, t, depth, hit, normal=None, steps=None, status=None,
+               stream=None):
+    """Multiscale sphere tracing into caller-allocated tensors (see include/nnm.h)."""
+    import torch
+    n = int(o.shape[0]) if hasattr(o, "shape") else 0
+    dev = stack.device
+    args = [
+        _dev_ptr(o, torch.float32, (n, 3), "o", dev, False),
+        _dev_ptr(v, torch.float32, (n, 3), "v", dev, False),
+        _dev_ptr(t, torch.float32, (n,), "t", dev),
+        _dev_ptr(depth, torch.float32, (n,), "depth", dev, False),
+        _dev_ptr(hit, torch.uint8, (n,), "hit", dev, False),
+        _dev_ptr(normal, torch.float32, (n, 3), "normal", dev),
+        _dev_ptr(steps, torch.uint8, (n, stack.m), "steps", dev),
+        _dev_ptr(status, torch.uint8, (n,), "status", dev),
+    ]
+    cp = params.c(stack.m)
+    _check(load_library().trace_rays(stack.handle, ctypes.cast(ctypes.byref(cp), c_void_p), n, *args,
+                                     _stream_ptr(stream, dev)))
+
+
+def analytic_normal(stack: Stack, level: int, x, t, value, grad, stream=None):
+    import torch
+    n = int(x.shape[0])
+    dev = stack.device
+    _check(load_library().analytic_normal(
+        stack.handle, int(level), n, _dev_ptr(x, torch.float32, (n, 3), "x", dev, False),
+        _dev_ptr(t, torch.float32, (n,), "t", dev), _dev_ptr(value, torch.float32, (n,), "value", dev),
+        _dev_ptr(grad, torch.float32, (n, 3), "grad", dev, False), _stream_ptr(stream, dev)))
+
+
+def nnm_net_eval(stack: Stack, level: int, x, t, value, grad, stream=None):
+    import torch
+    n = int(x.shape[0])
+    dev = stack.device
+    _check(load_library().nnm_net_eval(
+        stack.handle, int(level), n, _dev_ptr(x, torch.float32, (n, 3), "x", dev, False),
+        _dev_ptr(t, torch.float32, (n,), "t", dev), _dev_ptr(value, torch.float32, (n,), "value", dev),
+        _dev_ptr(grad, torch.float32, (n, 3), "grad", dev), _stream_ptr(stream, dev)))
+
+
+def nnm_sync(stream=None, device: int = 0):
+    _check(load_library().nnm_sync(_stream_ptr(stream, device)))
+
+
+def nnm_read_net_file(path: str):
+    """(d_in, width, n_sine, float32 params) parsed by the library."""
+    lib = load_library()
+    d_in, width, n_sine = c_int32(), c_int32(), c_int32()
+    buf = ctypes.POINTER(c_float)()
+    npar = c_int64()
+    _check(lib.nnm_read_net_file(str(path).encode(), ctypes.cast(ctypes.byref(d_in), c_void_p),
+                                 ctypes.cast(ctypes.byref(width), c_void_p),
+                                 ctypes.cast(ctypes.byref(n_sine), c_void_p),
+                                 ctypes.cast(ctypes.byref(buf), c_void_p),
+                                 ctypes.cast(ctypes.byref(npar), c_void_p)))
+    try:
+        arr = np.ctypeslib.as_array(buf, shape=(npar.value,)).copy()
+    finally:
+        lib.nnm_free(ctypes.cast(buf, c_void_p))
+    return d_in.value, width.value, n_sine.value, arr
+
+
+def render(stack: Stack, o, v, t=None, params: Optional[TraceParams] = None, want_normal=True, stream=None):
+    """Allocate outputs on the stack's device and trace; returns a dict of tensors."""
+    import torch
+    params = params or TraceParams()
+    n = int(o.shape[0])
+    dev = torch.device("cuda", stack.device)
+    out = {
+        "depth": torch.empty(n, dtype=torch.float32, device=dev),
+        "hit": torch.empty(n, dtype=torch.uint8, device=dev),
+        "normal": torch.empty((n, 3), dtype=torch.float32, device=dev) if want_normal else None,
+        "steps": torch.empty((n, stack.m), dtype=torch.uint8, device=dev),
+        "status": torch.empty(n, dtype=torch.uint8, device=dev),
+    }
+    trace_rays(stack, params, o, v, t, out["depth"], out["hit"], out["normal"], out["steps"], out["status"],
+               stream)
+    return out

@@ -1,0 +1,667 @@
+// nnm_api.cpp -- host side of libnnm's C ABI (include/nnm.h): validation,
+// Lipschitz bounds, weight packing for the gfx950 kernels, and the launch
+// sequence of multiscale sphere tracing.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nnm.h"
+#include "nnm_kernels.h"
+
+using namespace nnm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(NNM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr double kTwoPiD = 6.283185307179586476925286766559;
+
+// Switches to a device for the lifetime of the guard.
+struct DeviceGuard {
+  int old = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old) != hipSuccess) old = -1;
+    if (old != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (old >= 0) (void)hipSetDevice(old);
+  }
+};
+
+bool width_supported(int w) { return w == 32 || w == 64 || w == 128 || w == 256; }
+
+// Shapes of the affine layers of a network: layer i is rows[i] x cols[i].
+void layer_shape(int d_in, int width, int n_sine, int i, int* rows, int* cols) {
+  *rows = (i == n_sine) ? 1 : width;
+  *cols = (i == 0) ? d_in : width;
+}
+
+int64_t param_count(int d_in, int width, int n_sine) {
+  int64_t total = 0;
+  for (int i = 0; i <= n_sine; ++i) {
+    int r, c;
+    layer_shape(d_in, width, n_sine, i, &r, &c);
+    total += (int64_t)r * c + r;
+  }
+  return total;
+}
+
+// Offsets of W_i and b_i in the flat parameter vector.
+void layer_offsets(int d_in, int width, int n_sine, int i, int64_t* w_off, int64_t* b_off) {
+  int64_t off = 0;
+  for (int q = 0; q < i; ++q) {
+    int r, c;
+    layer_shape(d_in, width, n_sine, q, &r, &c);
+    off += (int64_t)r * c + r;
+  }
+  int r, c;
+  layer_shape(d_in, width, n_sine, i, &r, &c);
+  *w_off = off;
+  *b_off = off + (int64_t)r * c;
+}
+
+// Largest singular value of the rows x ncols block (leading columns of a
+// rows x ld row-major matrix) by power iteration on W^T W in float64.
+double spectral_norm(const float* W, int rows, int ld, int ncols) {
+  std::vector<double> v(ncols), u(rows), w(ncols);
+  for (int j = 0; j < ncols; ++j) v[j] = 1.0 + 0.01 * ((j * 37) % 11);
+  double lam = 0.0;
+  for (int it = 0; it < 1000; ++it) {
+    double nv = 0.0;
+    for (int j = 0; j < ncols; ++j) nv += v[j] * v[j];
+    nv = std::sqrt(nv);
+    if (nv == 0.0) return 0.0;
+    for (int j = 0; j < ncols; ++j) v[j] /= nv;
+    for (int r = 0; r < rows; ++r) {
+      double s = 0.0;
+      for (int j = 0; j < ncols; ++j) s += (double)W[(size_t)r * ld + j] * v[j];
+      u[r] = s;
+    }
+    for (int j = 0; j < ncols; ++j) w[j] = 0.0;
+    for (int r = 0; r < rows; ++r)
+      for (int j = 0; j < ncols; ++j) w[j] += (double)W[(size_t)r * ld + j] * u[r];
+    double nl = 0.0;
+    for (int j = 0; j < ncols; ++j) nl += w[j] * v[j];
+    v.swap(w);
+    if (it > 10 && std::fabs(nl - lam) <= 1e-13 * std::fabs(nl)) {
+      lam = nl;
+      break;
+    }
+    lam = nl;
+  }
+  return std::sqrt(std::max(lam, 0.0));
+}
+
+double lipschitz_bound(const nnm_level_desc& L, int base_sphere) {
+  double prod = 1.0;
+  for (int i = 0; i <= L.n_sine; ++i) {
+    int r, c;
+    layer_shape(L.d_in, L.width, L.n_sine, i, &r, &c);
+    int64_t wo, bo;
+    layer_offsets(L.d_in, L.width, L.n_sine, i, &wo, &bo);
+    prod *= spectral_norm(L.params + wo, r, c, i == 0 ? 3 : c);
+  }
+  return (base_sphere ? 1.0 : 0.0) + std::fabs((double)L.amplitude) * prod;
+}
+
+int validate_level(const nnm_level_desc& L, int j) {
+  if (L.d_in != 3 && L.d_in != 4) return fail(NNM_E_UNSUPPORTED, "level %d: d_in %d (3 or 4 supported)", j, L.d_in);
+  if (!width_supported(L.width))
+    return fail(NNM_E_UNSUPPORTED, "level %d: width %d (32, 64, 128, 256 supported)", j, L.width);
+  if (L.n_sine < 1 || L.n_sine > kMaxSine)
+    return fail(NNM_E_UNSUPPORTED, "level %d: %d sine layers (1..%d supported)", j, L.n_sine, kMaxSine);
+  if (!L.params) return fail(NNM_E_INVAL, "level %d: null params", j);
+  if (!std::isfinite(L.amplitude)) return fail(NNM_E_NONFINITE, "level %d: non-finite amplitude", j);
+  if (!std::isfinite(L.delta)) return fail(NNM_E_NONFINITE, "level %d: non-finite delta", j);
+  const int64_t np = param_count(L.d_in, L.width, L.n_sine);
+  for (int64_t k = 0; k < np; ++k)
+    if (!std::isfinite(L.params[k])) return fail(NNM_E_NONFINITE, "level %d: non-finite parameter %lld", j, (long long)k);
+  return NNM_OK;
+}
+
+uint16_t to_bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+uint16_t to_f16_rne(float x) {
+  _Float16 h = (_Float16)x;  // round to nearest even
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct nnm_profiler {
+  struct Rec {
+    int kind, level, width;
+    hipEvent_t start, stop;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;  // reusable events
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void clear() {
+    for (auto& r : recs) {
+      pool.push_back(r.start);
+      pool.push_back(r.stop);
+    }
+    recs.clear();
+  }
+  ~nnm_profiler() {
+    clear();
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+// Records an event pair around one launch when a profiler is attached.
+struct ProfScope {
+  nnm_profiler* p;
+  nnm_profiler::Rec rec{};
+  hipStream_t s;
+  ProfScope(nnm_profiler* prof, int kind, int level, int width, hipStream_t st) : p(prof), s(st) {
+    if (!p) return;
+    rec.kind = kind;
+    rec.level = level;
+    rec.width = width;
+    rec.start = p->get();
+    rec.stop = p->get();
+    if (rec.start) (void)hipEventRecord(rec.start, s);
+  }
+  ~ProfScope() {
+    if (!p || !rec.start || !rec.stop) return;
+    (void)hipEventRecord(rec.stop, s);
+    p->recs.push_back(rec);
+  }
+};
+}  // namespace
+
+struct nnm_stack {
+  int device = 0;
+  int precision = 0;
+  int m = 0;
+  DevBase base{};
+  struct Level {
+    int d_in, width, n_sine, follow_center;
+    float amplitude, delta;
+    DevLevel dev{};
+    void* mem = nullptr;
+    int resident[3] = {1, 1, 1};
+  };
+  std::vector<Level> levels;
+};
+
+extern "C" {
+
+const char* nnm_last_error(void) { return g_err.c_str(); }
+
+const char* nnm_version(void) { return "libnnm 0.1 (gfx950)"; }
+
+void nnm_free(void* p) { std::free(p); }
+
+int64_t nnm_param_count(int32_t d_in, int32_t width, int32_t n_sine) {
+  if ((d_in != 3 && d_in != 4) || width < 1 || n_sine < 1 || n_sine > kMaxSine) return -1;
+  return param_count(d_in, width, n_sine);
+}
+
+int nnm_level_lipschitz_bound(const nnm_level_desc* level, int base_sphere, double* bound) {
+  if (!level || !bound) return fail(NNM_E_INVAL, "null argument");
+  const int rc = validate_level(*level, 0);
+  if (rc != NNM_OK) return rc;
+  *bound = lipschitz_bound(*level, base_sphere);
+  return NNM_OK;
+}
+
+int nnm_validate_stack(const nnm_stack_desc* d, int precision) {
+  g_err.clear();
+  if (!d) return fail(NNM_E_INVAL, "null stack descriptor");
+  if (precision < NNM_PREC_FP32 || precision > NNM_PREC_FP16)
+    return fail(NNM_E_UNSUPPORTED, "precision %d (0 fp32, 1 bf16, 2 fp16)", precision);
+  if (d->n_levels < 1 || d->n_levels > kMaxLevels)
+    return fail(NNM_E_INVAL, "n_levels %d (1..%d)", d->n_levels, kMaxLevels);
+  if (!d->levels) return fail(NNM_E_INVAL, "null levels");
+  if (!std::isfinite(d->r0) || !std::isfinite(d->rho) || !std::isfinite(d->lipschitz_max))
+    return fail(NNM_E_NONFINITE, "non-finite base parameters");
+  if (d->lipschitz_max < 0.f) return fail(NNM_E_INVAL, "negative lipschitz_max");
+  for (int j = 0; j < d->n_levels; ++j) {
+    const int rc = validate_level(d->levels[j], j);
+    if (rc != NNM_OK) return rc;
+  }
+  // Nesting thresholds (Eq.(1)): delta_1 > delta_2 > ... > delta_{m-1} > 0.
+  for (int j = 0; j + 1 < d->n_levels; ++j) {
+    if (!(d->levels[j].delta > 0.f)) return fail(NNM_E_NESTING, "level %d: delta %g must be > 0", j, d->levels[j].delta);
+    if (j > 0 && !(d->levels[j].delta < d->levels[j - 1].delta))
+      return fail(NNM_E_NESTING, "level %d: delta %g not below delta %g of level %d", j, d->levels[j].delta,
+                  d->levels[j - 1].delta, j - 1);
+  }
+  if (d->lipschitz_max > 0.f) {
+    for (int j = 0; j < d->n_levels; ++j) {
+      const double b = lipschitz_bound(d->levels[j], d->base_sphere);
+      if (b > (double)d->lipschitz_max * (1.0 + 1e-6))
+        return fail(NNM_E_LIPSCHITZ, "level %d: Lipschitz bound %.6f exceeds %.6f", j, b, (double)d->lipschitz_max);
+    }
+  }
+  return NNM_OK;
+}
+
+static int pack_level(const nnm_level_desc& L, int precision, int device, nnm_stack::Level* out) {
+  const int H = L.width, K = L.n_sine, MB = H / 32;
+  // Host staging of every packed table.
+  std::vector<float> a0(3 * MB * 64, 0.f);
+  std::vector<float> bh((size_t)std::max(K - 1, 1) * H, 0.f);
+  std::vector<float> wk(H, 0.f);
+  const size_t elem = precision == NNM_PREC_FP32 ? 4 : 2;
+  const size_t ah_stride = align256((size_t)H * H * elem);
+  std::vector<uint8_t> ah((size_t)std::max(K - 1, 1) * ah_stride, 0);
+
+  int64_t wo, bo;
+  layer_offsets(L.d_in, H, K, 0, &wo, &bo);
+  const float* W0 = L.params + wo;
+  const float* b0 = L.params + bo;
+  const int ncol0 = L.d_in + 1;  // augmented columns: inputs, then the bias
+  for (int ks = 0; ks < 3; ++ks)
+    for (int mb = 0; mb < MB; ++mb)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int i = lane % 32, g = lane / 32, k = 2 * ks + g;
+        const int row = 32 * mb + i;
+        double v = 0.0;
+        if (k < L.d_in)
+          v = (double)W0[(size_t)row * L.d_in + k];
+        else if (k == L.d_in)
+          v = (double)b0[row];
+        (void)ncol0;
+        a0[a0_index(ks, mb, lane, MB)] = (float)(v / kTwoPiD);
+      }
+  double hidden_arg = 0.0;  // bound of |hidden pre-activation| in revolutions
+  for (int layer = 1; layer < K; ++layer) {
+    layer_offsets(L.d_in, H, K, layer, &wo, &bo);
+    const float* W = L.params + wo;
+    const float* b = L.params + bo;
+    for (int mb = 0; mb < MB; ++mb)
+      for (int g = 0; g < 2; ++g)
+        for (int r = 0; r < 16; ++r)
+          bh[(size_t)(layer - 1) * H + acc_slot(mb, g, r)] = (float)((double)b[acc_row(mb, g, r)] / kTwoPiD);
+    for (int row = 0; row < H; ++row) {
+      double s = std::fabs((double)b[row]);
+      for (int c = 0; c < H; ++c) s += std::fabs((double)W[(size_t)row * H + c]);
+      hidden_arg = std::max(hidden_arg, s / kTwoPiD);
+    }
+    uint8_t* dst = ah.data() + (size_t)(layer - 1) * ah_stride;
+    auto wscaled = [&](int row, int col) { return (float)((double)W[(size_t)row * H + col] / kTwoPiD); };
+    if (precision == NNM_PREC_FP32) {
+      float* A = (float*)dst;
+      for (int q = 0; q < H / 8; ++q)
+        for (int mb = 0; mb < MB; ++mb)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int e = 0; e < 4; ++e) {
+              const int i = lane % 32, g = lane / 32, ks = 4 * q + e;
+              A[(((size_t)q * MB + mb) * 64 + lane) * 4 + e] = wscaled(32 * mb + i, kperm_2(ks, g));
+            }
+    } else {
+      uint16_t* A = (uint16_t*)dst;
+      for (int ks = 0; ks < 2 * MB; ++ks)
+        for (int mb = 0; mb < MB; ++mb)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int e = 0; e < 8; ++e) {
+              const int i = lane % 32, g = lane / 32;
+              const float w = wscaled(32 * mb + i, kperm_16(ks, g, e));
+              A[(((size_t)ks * MB + mb) * 64 + lane) * 8 + e] =
+                  precision == NNM_PREC_BF16 ? to_bf16_rne(w) : to_f16_rne(w);
+            }
+    }
+  }
+  layer_offsets(L.d_in, H, K, K, &wo, &bo);
+  for (int mb = 0; mb < MB; ++mb)
+    for (int g = 0; g < 2; ++g)
+      for (int r = 0; r < 16; ++r) wk[acc_slot(mb, g, r)] = L.params[wo + acc_row(mb, g, r)];
+  const float bk = L.params[bo];
+
+  // One device allocation per level.
+  const size_t off_a0 = 0;
+  const size_t off_bh = off_a0 + align256(a0.size() * 4);
+  const size_t off_wk = off_bh + align256(bh.size() * 4);
+  const size_t off_ah = off_wk + align256(wk.size() * 4);
+  const size_t total = off_ah + ah.size();
+  void* mem = nullptr;
+  hipError_t e = hipMalloc(&mem, total);
+  if (e != hipSuccess) return fail(NNM_E_NOMEM, "hipMalloc(%zu): %s", total, hipGetErrorString(e));
+  char* base = (char*)mem;
+  if ((e = hipMemcpy(base + off_a0, a0.data(), a0.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(base + off_bh, bh.data(), bh.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(base + off_wk, wk.data(), wk.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(base + off_ah, ah.data(), ah.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(mem);
+    return hip_fail(e, "uploading packed weights");
+  }
+  out->d_in = L.d_in;
+  out->width = H;
+  out->n_sine = K;
+  out->follow_center = L.follow_center ? 1 : 0;
+  out->amplitude = L.amplitude;
+  out->delta = L.delta;
+  out->mem = mem;
+  DevLevel& D = out->dev;
+  D.a0 = (const float*)(base + off_a0);
+  D.bh = (const float*)(base + off_bh);
+  D.wk = (const float*)(base + off_wk);
+  D.ah = (const void*)(base + off_ah);
+  D.ah_stride = (long long)ah_stride;
+  D.bk = bk;
+  D.amplitude = L.amplitude;
+  D.delta = L.delta;
+  D.d_in = L.d_in;
+  D.width = H;
+  D.n_sine = K;
+  D.follow_center = out->follow_center;
+  D.reduce_hidden = hidden_arg > 64.0 ? 1 : 0;
+  for (int kind = 0; kind < 3; ++kind) out->resident[kind] = resident_blocks(H, precision, kind, device);
+  return NNM_OK;
+}
+
+void free_siren_stack(nnm_stack* s) {
+  if (!s) return;
+  DeviceGuard guard(s->device);
+  for (auto& L : s->levels)
+    if (L.mem) (void)hipFree(L.mem);
+  delete s;
+}
+
+int load_siren_stack(const nnm_stack_desc* d, int precision, int device, nnm_stack** out) {
+  if (!out) return fail(NNM_E_INVAL, "null output handle");
+  *out = nullptr;
+  int rc = nnm_validate_stack(d, precision);
+  if (rc != NNM_OK) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(NNM_E_DEVICE, "no HIP device");
+  if (device < 0 || device >= ndev) return fail(NNM_E_INVAL, "device %d of %d", device, ndev);
+  DeviceGuard guard(device);
+  if (!guard.ok) return fail(NNM_E_DEVICE, "hipSetDevice(%d) failed", device);
+  nnm_stack* s = new nnm_stack();
+  s->device = device;
+  s->precision = precision;
+  s->m = d->n_levels;
+  s->base.sphere = d->base_sphere ? 1 : 0;
+  s->base.r0 = d->r0;
+  s->base.rho = d->rho;
+  s->levels.resize(d->n_levels);
+  for (int j = 0; j < d->n_levels; ++j) {
+    rc = pack_level(d->levels[j], precision, device, &s->levels[j]);
+    if (rc != NNM_OK) {
+      free_siren_stack(s);
+      return rc;
+    }
+  }
+  *out = s;
+  return NNM_OK;
+}
+
+int nnm_stack_levels(const nnm_stack* s) { return s ? s->m : -1; }
+int nnm_stack_precision(const nnm_stack* s) { return s ? s->precision : -1; }
+
+int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const float* o, const float* v,
+               const float* t, float* depth, uint8_t* hit, float* normal, uint8_t* steps, uint8_t* status,
+               void* stream) {
+  g_err.clear();
+  if (!s || !p) return fail(NNM_E_INVAL, "null stack or params");
+  if (n < 0) return fail(NNM_E_INVAL, "n = %lld < 0", (long long)n);
+  if (n > (int64_t)INT_MAX - (1 << 24)) return fail(NNM_E_INVAL, "n = %lld too large", (long long)n);
+  if (p->final_level < 0 || p->final_level >= s->m)
+    return fail(NNM_E_INVAL, "final_level %d of %d levels", p->final_level, s->m);
+  if (p->normal_level < 0 || p->normal_level >= s->m)
+    return fail(NNM_E_INVAL, "normal_level %d of %d levels", p->normal_level, s->m);
+  if (!(p->step_scale > 0.f && p->step_scale <= 1.f)) return fail(NNM_E_INVAL, "step_scale %g not in (0, 1]", p->step_scale);
+  if (!(p->eps > 0.f) || !std::isfinite(p->eps)) return fail(NNM_E_INVAL, "eps %g", p->eps);
+  if (!(p->far > 0.f) || !std::isfinite(p->far)) return fail(NNM_E_INVAL, "far %g", p->far);
+  if (p->max_steps < 1 || p->max_steps > 255) return fail(NNM_E_INVAL, "max_steps %d not in 1..255", p->max_steps);
+  if (p->mode != 0) return fail(NNM_E_UNSUPPORTED, "trace mode %d", p->mode);
+  if (n == 0) return NNM_OK;
+  if (!o || !v || !depth || !hit) return fail(NNM_E_INVAL, "null ray or output array");
+  DeviceGuard guard(s->device);
+  if (!guard.ok) return fail(NNM_E_DEVICE, "hipSetDevice(%d) failed", s->device);
+  hipStream_t st = (hipStream_t)stream;
+  const int L = p->final_level + 1;
+  // Scratch: counters (head and out count per level), two ping-pong queues,
+  // and the status carrier when the caller passes none.
+  const size_t off_cnt = 0;
+  const size_t off_qa = 256;
+  const size_t off_qb = off_qa + align256((size_t)n * 4);
+  const size_t off_st = off_qb + align256((size_t)n * 4);
+  const size_t total = off_st + (status ? 0 : align256((size_t)n));
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, total, st);
+  if (e != hipSuccess) return fail(NNM_E_NOMEM, "hipMallocAsync(%zu): %s", total, hipGetErrorString(e));
+  char* wb = (char*)ws;
+  int* cnt = (int*)(wb + off_cnt);  // cnt[2j]: pop head of level j, cnt[2j+1]: rays out of level j
+  int* q[2] = {(int*)(wb + off_qa), (int*)(wb + off_qb)};
+  uint8_t* stat = status ? status : (uint8_t*)(wb + off_st);
+  int rc = NNM_OK;
+  if ((e = launch_zero_ints(cnt, 64, st)) != hipSuccess) rc = hip_fail(e, "zeroing counters");
+  for (int j = 0; j < L && rc == NNM_OK; ++j) {
+    const auto& lv = s->levels[j];
+    TraceLevelArgs a{};
+    a.L = lv.dev;
+    a.B = s->base;
+    a.o = o;
+    a.v = v;
+    a.t = t;
+    a.depth = depth;
+    a.hit = hit;
+    a.normal = normal;
+    a.steps = steps;
+    a.status = stat;
+    a.in_queue = j == 0 ? nullptr : q[(j - 1) & 1];
+    a.in_count = j == 0 ? nullptr : cnt + 2 * (j - 1) + 1;
+    a.in_head = cnt + 2 * j;
+    const bool is_final = (j == L - 1);
+    a.out_queue = (!is_final || normal) ? q[j & 1] : nullptr;
+    a.out_count = cnt + 2 * j + 1;
+    a.n = (int)n;
+    a.level = j;
+    a.m = s->m;
+    a.is_final = is_final ? 1 : 0;
+    a.max_steps = p->max_steps;
+    a.step_scale = p->step_scale;
+    a.eps = p->eps;
+    a.far = p->far;
+    a.delta = is_final ? 0.f : lv.delta;
+    const long long want = ((long long)n + 127) / 128;
+    const int grid = (int)std::max(1LL, std::min(want, (long long)lv.resident[0]));
+    ProfScope prof(p->profiler, 0, j, lv.width, st);
+    if ((e = launch_trace_level(lv.width, s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "trace level");
+  }
+  if (rc == NNM_OK && normal) {
+    const auto& nl = s->levels[p->normal_level];
+    NormalArgs a{};
+    a.L = nl.dev;
+    a.B = s->base;
+    a.o = o;
+    a.v = v;
+    a.t = t;
+    a.depth = depth;
+    a.normal = normal;
+    a.queue = q[(L - 1) & 1];
+    a.count = cnt + 2 * (L - 1) + 1;
+    a.n = (int)n;
+    const long long want = ((long long)n + 31) / 32;
+    const int grid = (int)std::max(1LL, std::min(want, (long long)nl.resident[1]));
+    ProfScope prof(p->profiler, 1, p->normal_level, nl.width, st);
+    if ((e = launch_normal(nl.width, s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "normal pass");
+  }
+  if ((e = hipFreeAsync(ws, st)) != hipSuccess && rc == NNM_OK) rc = hip_fail(e, "hipFreeAsync");
+  return rc;
+}
+
+static int points_common(const nnm_stack* s, int level, int64_t n, const float* x, const float* t, float* value,
+                         float* grad, void* stream, int raw) {
+  g_err.clear();
+  if (!s) return fail(NNM_E_INVAL, "null stack");
+  if (level < 0 || level >= s->m) return fail(NNM_E_INVAL, "level %d of %d", level, s->m);
+  if (n < 0) return fail(NNM_E_INVAL, "n = %lld < 0", (long long)n);
+  if (n > (int64_t)INT_MAX - (1 << 24)) return fail(NNM_E_INVAL, "n = %lld too large", (long long)n);
+  if (n == 0) return NNM_OK;
+  if (!x) return fail(NNM_E_INVAL, "null points");
+  if (!value && !grad) return fail(NNM_E_INVAL, "no output requested");
+  DeviceGuard guard(s->device);
+  if (!guard.ok) return fail(NNM_E_DEVICE, "hipSetDevice(%d) failed", s->device);
+  const auto& lv = s->levels[level];
+  PointsArgs a{};
+  a.L = lv.dev;
+  a.B = s->base;
+  a.x = x;
+  a.t = t;
+  a.value = value;
+  a.grad = grad;
+  a.n = (int)n;
+  a.raw = raw;
+  const long long want = ((long long)n + 31) / 32;
+  const int grid = (int)std::max(1LL, std::min(want, (long long)lv.resident[2]));
+  const hipError_t e = launch_points(lv.width, s->precision, a, grid, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "point evaluation");
+  return NNM_OK;
+}
+
+int analytic_normal(const nnm_stack* s, int level, int64_t n, const float* x, const float* t, float* value,
+                    float* grad, void* stream) {
+  if (!grad && n > 0) return fail(NNM_E_INVAL, "null gradient output");
+  return points_common(s, level, n, x, t, value, grad, stream, 0);
+}
+
+int nnm_net_eval(const nnm_stack* s, int level, int64_t n, const float* x, const float* t, float* value,
+                 float* grad, void* stream) {
+  return points_common(s, level, n, x, t, value, grad, stream, 1);
+}
+
+int nnm_profiler_create(nnm_profiler** out) {
+  if (!out) return fail(NNM_E_INVAL, "null output handle");
+  *out = new nnm_profiler();
+  return NNM_OK;
+}
+
+void nnm_profiler_free(nnm_profiler* prof) { delete prof; }
+
+int nnm_profiler_reset(nnm_profiler* prof) {
+  if (!prof) return fail(NNM_E_INVAL, "null profiler");
+  prof->clear();
+  return NNM_OK;
+}
+
+int nnm_profiler_report(nnm_profiler* prof, nnm_profile_report* out) {
+  if (!prof || !out) return fail(NNM_E_INVAL, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  for (auto& r : prof->recs) {
+    hipError_t e = hipEventSynchronize(r.stop);
+    if (e != hipSuccess) return hip_fail(e, "profiler event");
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, r.start, r.stop);
+    if (e != hipSuccess) return hip_fail(e, "profiler elapsed time");
+    int slot = -1;
+    for (int i = 0; i < out->n_entries; ++i)
+      if (out->kind[i] == r.kind && out->level[i] == r.level) slot = i;
+    if (slot < 0) {
+      if (out->n_entries >= NNM_PROF_MAX) continue;
+      slot = out->n_entries++;
+      out->kind[slot] = r.kind;
+      out->level[slot] = r.level;
+      out->width[slot] = r.width;
+    }
+    out->launches[slot] += 1;
+    out->total_ms[slot] += ms;
+  }
+  return NNM_OK;
+}
+
+int nnm_sync(void* stream) {
+  const hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  const hipError_t e2 = hipGetLastError();
+  if (e2 != hipSuccess) return hip_fail(e2, "pending device error");
+  return NNM_OK;
+}
+
+int nnm_read_net_file(const char* path, int32_t* d_in, int32_t* width, int32_t* n_sine, float** params_out,
+                      int64_t* n_params) {
+  g_err.clear();
+  if (!path || !d_in || !width || !n_sine || !params_out || !n_params) return fail(NNM_E_INVAL, "null argument");
+  *params_out = nullptr;
+  FILE* fh = std::fopen(path, "rb");
+  if (!fh) return fail(NNM_E_IO, "cannot open %s", path);
+  uint32_t hdr[8];
+  char magic[4];
+  if (std::fread(magic, 1, 4, fh) != 4 || std::fread(hdr, 4, 7, fh) != 7) {
+    std::fclose(fh);
+    return fail(NNM_E_FORMAT, "%s: short header", path);
+  }
+  if (std::memcmp(magic, "NNMW", 4) != 0) {
+    std::fclose(fh);
+    return fail(NNM_E_FORMAT, "%s: bad magic", path);
+  }
+  if (hdr[0] != 1) {
+    std::fclose(fh);
+    return fail(NNM_E_FORMAT, "%s: version %u", path, hdr[0]);
+  }
+  const int di = (int)hdr[1], w = (int)hdr[2], ns = (int)hdr[3];
+  if ((di != 3 && di != 4) || w < 1 || w > 4096 || ns < 1 || ns > kMaxSine) {
+    std::fclose(fh);
+    return fail(NNM_E_FORMAT, "%s: shape d_in %d width %d n_sine %d", path, di, w, ns);
+  }
+  const int64_t np = param_count(di, w, ns);
+  float* buf = (float*)std::malloc((size_t)np * 4);
+  if (!buf) {
+    std::fclose(fh);
+    return fail(NNM_E_NOMEM, "malloc");
+  }
+  const size_t got = std::fread(buf, 4, (size_t)np, fh);
+  char extra;
+  const bool trailing = std::fread(&extra, 1, 1, fh) == 1;
+  std::fclose(fh);
+  if (got != (size_t)np || trailing) {
+    std::free(buf);
+    return fail(NNM_E_FORMAT, "%s: %zu parameters, expected %lld%s", path, got, (long long)np,
+                trailing ? " (trailing bytes)" : "");
+  }
+  *d_in = di;
+  *width = w;
+  *n_sine = ns;
+  *params_out = buf;
+  *n_params = np;
+  return NNM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// nnm_device.h -- device-side network description shared by the host packer
+// and the gfx950 kernels of libnnm.
+//
+// Tile model.  One wavefront (64 lanes) evaluates a SIREN (Eq.(2) of the paper,
+// phi = sin) on a tile of 32 columns.  Lane l owns column n = l % 32 and half
+// g = l / 32.  Every layer's pre-activations live in the accumulator layout of
+// the 32x32 MFMA: for row block mb (32 neurons) a lane holds the 16 rows
+//     row(mb, g, r) = 32 mb + 8 (r / 4) + 4 g + (r % 4),   r = 0..15,
+// so one layer's outputs are the next layer's B operand without leaving the
+// registers; the K order this implies is baked into the packed weights.
+//
+// Columns are either 32 independent points (forward-only) or 8 points with
+// four columns each [h | G_x G_y G_z] (forward plus the three tangent columns
+// of the analytic normal, Alg. 2 with one shared forward).
+//
+// Sine layers run in revolutions: W_0..W_{K-1} and b_0..b_{K-1} are packed
+// divided by 2 pi, so v_sin_f32 / v_cos_f32 (which take revolutions) apply
+// directly; the tangent columns carry the 2 pi back explicitly.
+#pragma once
+#include <stdint.h>
+
+namespace nnm {
+
+enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP16 = 2 };
+
+constexpr int kMaxLevels = 8;
+constexpr int kMaxSine = 8;
+constexpr int kWaveCols = 32;       // columns per wave tile
+constexpr int kBlockThreads = 256;  // 4 waves per workgroup
+
+// Index of the accumulator-layout slot (mb, g, r) in a [H] array.
+__host__ __device__ inline int acc_slot(int mb, int g, int r) { return (mb * 2 + g) * 16 + r; }
+__host__ __device__ inline int acc_row(int mb, int g, int r) { return 32 * mb + 8 * (r / 4) + 4 * g + (r % 4); }
+
+// Input neuron feeding k-slot e of lane half g at k-step ks (bf16/fp16 32x32x16).
+__host__ __device__ inline int kperm_16(int ks, int g, int e) {
+  return 32 * (ks / 2) + 8 * (2 * (ks % 2) + e / 4) + 4 * g + (e % 4);
+}
+// Input neuron feeding lane half g at k-step ks (fp32 32x32x2).
+__host__ __device__ inline int kperm_2(int ks, int g) {
+  const int mb = ks / 16, r = ks % 16;
+  return 32 * mb + 8 * (r / 4) + 4 * g + (r % 4);
+}
+
+// Layer-0 A operand (32x32x2 fp32): for k-step ks (0..2), row block mb and lane
+// l = i + 32 g: [W_0 | b_0][32 mb + i][2 ks + g] / 2pi over the augmented input
+// columns (x, y, z, 1) or (x, y, z, t, 1, 0); zero past the last column.
+__host__ __device__ inline int a0_index(int ks, int mb, int lane, int MB) { return (ks * MB + mb) * 64 + lane; }
+
+struct DevLevel {
+  const float* a0;    // [3][H/32][64] layer-0 A operand (see a0_index)
+  const float* bh;    // [(K-1) H] acc layout: hidden biases / 2pi
+  const float* wk;    // [H] acc layout: output weights (unscaled)
+  const void* ah;     // packed MFMA A fragments of the hidden layers
+  long long ah_stride;  // bytes per hidden layer of `ah`
+  float bk;           // output bias
+  float amplitude;
+  float delta;
+  int d_in;
+  int width;
+  int n_sine;
+  int follow_center;
+  int reduce_hidden;  // 1: reduce hidden sine arguments with fract first
+};
+
+struct DevBase {
+  int sphere;
+  float r0;
+  float rho;
+};
+
+}  // namespace nnm

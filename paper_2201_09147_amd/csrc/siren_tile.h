@@ -1,0 +1,252 @@
+// siren_tile.h -- fused SIREN evaluator for one wavefront tile on gfx950.
+//
+// Evaluates N(p) = W_K h_K + b_K, h_0 = p, h_{i+1} = sin(W_i h_i + b_i) (the MLP
+// form of Eq.(2) with phi = sin) for the 32 columns of a wave tile:
+//   * layer 0 (d_in -> H) as 32x32x2 fp32 MFMAs over the augmented input
+//     (x, y, z[, t], 1): the bias rides in the A operand, the argument stays
+//     float32 (omega0 = 30 makes it large);
+//   * hidden layers (H -> H) as 32x32 MFMA GEMMs in the stack's precision:
+//     A = packed weights streamed from L2 (one 16-byte load per lane per
+//     32x32x16 bf16/fp16 instruction, or per four 32x32x2 fp32 instructions),
+//     B = the previous layer's activations held in registers, C = the bias;
+//   * sin on the VALU (v_sin_f32 in revolutions), converted to the MFMA input
+//     precision in registers;
+//   * output layer as a per-lane dot product plus one cross-half reduction.
+//
+// Tangent mode (TAN) carries the analytic normal of Sec. 5.1 in the same pass:
+// columns 4q+c hold [h | G_x G_y G_z] of point q.  Tangent column j enters
+// layer 0 as the unit vector e_j with 0 in the bias slot, so its accumulator is
+// W_0[:, j]; every layer then applies G_i = phi'(a_i) * (W_i G_{i-1}) -- the
+// commuted Hadamard form of Alg. 2 whose i = 0 case is the initial condition
+// G_0 = W_0[j] * phi'(a_0) -- with phi'(a_i) = cos taken from the primal column
+// of the same quad (DPP broadcast).  The output layer gives grad N = W_K G.
+// The forward is shared by the three tangent columns instead of being
+// recomputed per coordinate.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "nnm_device.h"
+
+namespace nnm {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr float kTwoPi = 6.28318530717958647692f;
+
+// Compiler barrier: memory operations are not moved across it, which keeps
+// loop-invariant table reads from being hoisted into long-lived registers.
+#define NNM_MEM_FENCE() __asm__ volatile("" ::: "memory")
+
+// Per-workgroup copy of the small per-network tables (read with broadcast).
+template <int H>
+struct NetSmem {
+  float wk[H];                   // output weights, accumulator layout
+  float bh[(kMaxSine - 1) * H];  // hidden biases / 2 pi, accumulator layout
+};
+
+template <int H>
+__device__ inline void stage_net(NetSmem<H>* sm, const DevLevel& L) {
+  for (int i = threadIdx.x; i < H; i += blockDim.x) sm->wk[i] = L.wk[i];
+  const int nb = (L.n_sine - 1) * H;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) sm->bh[i] = L.bh[i];
+  __syncthreads();
+}
+
+__device__ inline float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
+__device__ inline float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }
+__device__ inline float fract_rev(float r) { return __builtin_amdgcn_fractf(r); }
+
+// Value of lane 4*(l/4)+SEL broadcast to the four lanes of each quad.
+template <int SEL>
+__device__ inline float quad_bcast(float v) {
+  constexpr int ctrl = SEL | (SEL << 2) | (SEL << 4) | (SEL << 6);  // quad_perm [SEL x4]
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false));
+}
+
+template <int P>
+struct HiddenOps;
+
+template <>
+struct HiddenOps<PREC_BF16> {
+  typedef bf16x8_t frag_t;
+  static __device__ inline frag_t pack(const float* v) {
+    frag_t f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] = (__bf16)v[e];
+    return f;
+  }
+  static __device__ inline f32x16_t mfma(frag_t a, frag_t b, f32x16_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct HiddenOps<PREC_FP16> {
+  typedef f16x8_t frag_t;
+  static __device__ inline frag_t pack(const float* v) {
+    frag_t f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] = (_Float16)v[e];
+    return f;
+  }
+  static __device__ inline f32x16_t mfma(frag_t a, frag_t b, f32x16_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// Layer-0 B operand of k-step ks for lane half g: element 2 ks + g of the
+// augmented input (x, y, z, 1) or (x, y, z, t, 1, 0); tangent columns use the
+// unit vector of their coordinate with 0 in the bias and time slots.
+__device__ inline float layer0_input(float4 in, int d_in, int c, int ks, int g) {
+  const int k = 2 * ks + g;
+  if (c > 0) return (k == c - 1) ? 1.f : 0.f;
+  if (k < 3) return k == 0 ? in.x : (k == 1 ? in.y : in.z);
+  if (d_in == 4) return k == 3 ? in.w : (k == 4 ? 1.f : 0.f);
+  return k == 3 ? 1.f : 0.f;
+}
+
+template <int H, int P, bool TAN>
+struct SirenTile {
+  static constexpr int MB = H / 32;
+  float act[MB][16];  // activations of the current layer, accumulator layout
+
+  // h = sin(a) for primal columns; G = 2 pi v cos(a) for tangent columns, a the
+  // primal accumulator of the same quad.  Accumulators are in revolutions
+  // (weights / 2 pi); tangent accumulators carry (W / 2 pi) G, hence the 2 pi.
+  __device__ inline void activate(const f32x16_t* acc, int c, bool reduce) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float v = acc[mb][r];
+        if (TAN) {
+          float rp = quad_bcast<0>(v);
+          if (reduce) rp = fract_rev(rp);
+          const float sv = sin_rev(rp), cv = cos_rev(rp);
+          act[mb][r] = (c == 0) ? sv : (kTwoPi * v) * cv;
+        } else {
+          act[mb][r] = sin_rev(reduce ? fract_rev(v) : v);
+        }
+      }
+  }
+
+  __device__ inline void first_layer(const DevLevel& L, float4 in, int c) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 5;
+    const int ks0 = L.d_in == 4 ? 3 : 2;
+    f32x16_t acc[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mb][r] = 0.f;
+    const float* A = L.a0;
+#pragma unroll
+    for (int ks = 0; ks < 3; ++ks) {
+      if (ks < ks0) {
+        const float b = layer0_input(in, L.d_in, c, ks, g);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+          acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[(ks * MB + mb) * 64 + lane], b, acc[mb], 0, 0, 0);
+      }
+    }
+    activate(acc, c, true);
+  }
+
+  __device__ inline void hidden_layer(const NetSmem<H>* sm, const DevLevel& L, int layer, int c) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 5;
+    NNM_MEM_FENCE();
+    const float* bias = sm->bh + (layer - 1) * H;
+    // C = bias for primal columns; tangent columns carry W G only.
+    const bool primal = !TAN || c == 0;
+    f32x16_t acc[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mb][r] = primal ? bias[acc_slot(mb, g, r)] : 0.f;
+    const char* base = (const char*)L.ah + (long long)(layer - 1) * L.ah_stride;
+    // A fragments stream from L2 through a ring of kRing k-steps; scheduling
+    // barriers keep the compiler from issuing a whole layer of loads at once.
+    constexpr int kRing = 2;
+    if constexpr (P == PREC_FP32) {
+      // 32x32x2 fp32: k-step ks uses activation act[ks/16][ks%16]; four k-steps
+      // per 16-byte A load (group q).
+      constexpr int NQ = H / 8;
+      const f32x4_t* A = (const f32x4_t*)base;
+      f32x4_t ring[kRing][MB];
+#pragma unroll
+      for (int d = 0; d < kRing; ++d)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) ring[d][mb] = A[(d * MB + mb) * 64 + lane];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int ks = 4 * q + e;
+          const float b = act[ks / 16][ks % 16];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+            acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ring[q % kRing][mb][e], b, acc[mb], 0, 0, 0);
+        }
+        if (q + kRing < NQ) {
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) ring[q % kRing][mb] = A[((q + kRing) * MB + mb) * 64 + lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      typedef HiddenOps<P> Ops;
+      typedef typename Ops::frag_t frag_t;
+      constexpr int KS = 2 * MB;
+      frag_t bfr[KS];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        bfr[2 * mb] = Ops::pack(&act[mb][0]);
+        bfr[2 * mb + 1] = Ops::pack(&act[mb][8]);
+      }
+      const frag_t* A = (const frag_t*)base;
+      frag_t ring[kRing][MB];
+#pragma unroll
+      for (int d = 0; d < kRing; ++d)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) ring[d][mb] = A[(d * MB + mb) * 64 + lane];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = Ops::mfma(ring[ks % kRing][mb], bfr[ks], acc[mb]);
+        if (ks + kRing < KS) {
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) ring[ks % kRing][mb] = A[((ks + kRing) * MB + mb) * 64 + lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    activate(acc, c, L.reduce_hidden != 0);
+  }
+
+  // Returns, per lane, the output of its column after the cross-half reduction:
+  // forward mode N (same on both halves); tangent mode N for c == 0 and
+  // dN/dx_{c-1} for c = 1..3.
+  __device__ inline float eval(const NetSmem<H>* sm, const DevLevel& L, float4 in, int c) {
+    const int g = (threadIdx.x & 63) >> 5;
+    NNM_MEM_FENCE();
+    first_layer(L, in, c);
+    for (int layer = 1; layer < L.n_sine; ++layer) hidden_layer(sm, L, layer, c);
+    NNM_MEM_FENCE();
+    float part = 0.f;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) part = fmaf(sm->wk[acc_slot(mb, g, r)], act[mb][r], part);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    part += __shfl_xor(part, 32);
+    if (!TAN || c == 0) part += L.bk;
+    return part;
+  }
+};
+
+}  // namespace nnm

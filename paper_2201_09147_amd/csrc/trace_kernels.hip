@@ -1,0 +1,347 @@
+// trace_kernels.hip -- multiscale sphere tracing, analytic normals and point
+// evaluation kernels for gfx950.
+//
+// Multiscale sphere tracing (Algorithm 1 of the paper) runs one persistent
+// kernel per level.  Each wavefront owns 32 ray slots (one tile column each) and
+// loops: refill empty slots from the level's input queue (one atomic per wave),
+// evaluate f_j at all slots with the fused SIREN tile, step every live ray
+// (tau += s d with d = f_j - delta_j), and retire rays that left the level: to
+// the next level's queue (d <= eps), to the hit queue (last level), or as a miss
+// (tau > far, budget used, non-finite).  Slots freed by retired rays are refilled
+// on the next iteration, so tiles stay dense while the queue lasts and every
+// tile evaluates one network only.  The normal pass then evaluates the normal
+// level's forward and three tangent columns (Sec. 5.1) at the hit points.
+#include "nnm_kernels.h"
+#include "siren_tile.h"
+
+namespace nnm {
+
+__device__ inline float4 net_input(const DevLevel& L, float x, float y, float z, float t, float cx, float cy) {
+  if (L.d_in == 4) return make_float4(x, y, z, t);
+  if (L.follow_center) return make_float4(x - cx, y - cy, z, 0.f);
+  return make_float4(x, y, z, 0.f);
+}
+
+__device__ inline void center_at(const DevBase& B, float t, float& cx, float& cy) {
+  cx = 0.f;
+  cy = 0.f;
+  if (B.rho != 0.f) {
+    const float tr = fract_rev(t);
+    cx = B.rho * cos_rev(tr);
+    cy = B.rho * sin_rev(tr);
+  }
+}
+
+__global__ void k_zero_ints(int* p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+template <int H, int P>
+__global__ void __launch_bounds__(kBlockThreads) k_trace_level(TraceLevelArgs A) {
+  __shared__ NetSmem<H> sm;
+  stage_net<H>(&sm, A.L);
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 31;
+  const int g = lane >> 5;
+  const int n_in = A.in_count ? *A.in_count : A.n;
+  SirenTile<H, P, false> tile;
+  int ray = -1, k = 0, st = 0;
+  float tau = 0.f, ox = 0.f, oy = 0.f, oz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, tt = 0.f;
+  bool exhausted = false;
+  for (;;) {
+    // Refill empty slots from the input queue.  Both halves of a column hold
+    // the same slot state, so the lower half's ballot describes the slots.
+    if (!exhausted) {
+      const unsigned int emask = (unsigned int)__ballot(ray < 0);
+      const int cnt = __popc(emask);
+      if (cnt > 0) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(A.in_head, cnt);
+        base = __shfl(base, 0);
+        const int avail = n_in - base;
+        if (avail <= cnt) exhausted = true;
+        if (ray < 0) {
+          const int pos = __popc(emask & ((1u << col) - 1u));
+          if (pos < avail) {
+            const int idx = base + pos;
+            ray = A.in_queue ? A.in_queue[idx] : idx;
+            ox = A.o[3 * ray + 0];
+            oy = A.o[3 * ray + 1];
+            oz = A.o[3 * ray + 2];
+            vx = A.v[3 * ray + 0];
+            vy = A.v[3 * ray + 1];
+            vz = A.v[3 * ray + 2];
+            tt = A.t ? A.t[ray] : 0.f;
+            k = 0;
+            if (A.level == 0) {
+              tau = 0.f;
+              st = 0;
+              if (A.steps && g == 0)
+                for (int j = 1; j < A.m; ++j) A.steps[(long long)ray * A.m + j] = 0;
+            } else {
+              tau = A.depth[ray];
+              st = A.status[ray];
+            }
+          }
+        }
+      }
+    }
+    if (__ballot(ray >= 0) == 0ull) break;
+
+    const float x = fmaf(tau, vx, ox), y = fmaf(tau, vy, oy), z = fmaf(tau, vz, oz);
+    float cx, cy;
+    center_at(A.B, tt, cx, cy);
+    const float N = tile.eval(&sm, A.L, net_input(A.L, x, y, z, tt, cx, cy), 0);
+
+    int outcome = 0;  // 0: keep stepping, 1: left the level through d <= eps, 2: miss
+    if (ray >= 0) {
+      float base_term = 0.f;
+      if (A.B.sphere) {
+        const float dx = x - cx, dy = y - cy;
+        base_term = sqrtf(fmaf(dx, dx, fmaf(dy, dy, z * z))) - A.B.r0;
+      }
+      const float f = fmaf(A.L.amplitude, N, base_term);
+      const float d = f - A.delta;
+      ++k;
+      if (!isfinite(d)) {
+        st |= ST_NONFINITE;
+        outcome = 2;
+      } else {
+        if (d < 0.f) st |= ST_NEG_STEP;
+        tau = fmaf(A.step_scale, d, tau);
+        if (tau > A.far) {
+          st |= ST_FAR;
+          outcome = 2;
+        } else if (d <= A.eps) {
+          outcome = 1;
+        } else if (k >= A.max_steps) {
+          st |= ST_BUDGET;
+          outcome = 2;
+        }
+      }
+    }
+    // Compaction: rays that finished the level go to the output queue.
+    const unsigned int pmask = (unsigned int)__ballot(outcome == 1);
+    if (pmask && A.out_queue) {
+      int pbase = 0;
+      if (lane == 0) pbase = atomicAdd(A.out_count, __popc(pmask));
+      pbase = __shfl(pbase, 0);
+      if (outcome == 1 && g == 0) A.out_queue[pbase + __popc(pmask & ((1u << col) - 1u))] = ray;
+    }
+    if (outcome != 0) {
+      if (g == 0) {
+        if (A.steps) A.steps[(long long)ray * A.m + A.level] = (uint8_t)k;
+        if (outcome == 2) {
+          A.depth[ray] = __builtin_inff();
+          A.hit[ray] = 0;
+          A.status[ray] = (uint8_t)st;
+          if (A.normal) {
+            A.normal[3 * ray + 0] = 0.f;
+            A.normal[3 * ray + 1] = 0.f;
+            A.normal[3 * ray + 2] = 0.f;
+          }
+        } else if (A.is_final) {
+          A.depth[ray] = tau;
+          A.hit[ray] = 1;
+          A.status[ray] = (uint8_t)(st | ST_HIT);
+        } else {
+          A.depth[ray] = tau;
+          A.status[ray] = (uint8_t)st;
+        }
+      }
+      ray = -1;
+    }
+  }
+}
+
+// Forward + three tangent columns at the hit points; unit grad f as the normal.
+template <int H, int P>
+__global__ void __launch_bounds__(kBlockThreads) k_normal(NormalArgs A) {
+  __shared__ NetSmem<H> sm;
+  stage_net<H>(&sm, A.L);
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 31;
+  const int g = lane >> 5;
+  const int q = col >> 2, c = col & 3;
+  const int waves = kBlockThreads / 64;
+  const int wave = blockIdx.x * waves + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * waves;
+  const int n_in = A.count ? *A.count : A.n;
+  SirenTile<H, P, true> tile;
+  for (int base = wave * 8; base < n_in; base += nwaves * 8) {
+    const int slot = base + q;
+    const int ray = (slot < n_in) ? (A.queue ? A.queue[slot] : slot) : -1;
+    float x = 0.f, y = 0.f, z = 0.f, tt = 0.f;
+    if (ray >= 0) {
+      const float tau = A.depth[ray];
+      x = fmaf(tau, A.v[3 * ray + 0], A.o[3 * ray + 0]);
+      y = fmaf(tau, A.v[3 * ray + 1], A.o[3 * ray + 1]);
+      z = fmaf(tau, A.v[3 * ray + 2], A.o[3 * ray + 2]);
+      tt = A.t ? A.t[ray] : 0.f;
+    }
+    float cx, cy;
+    center_at(A.B, tt, cx, cy);
+    const float val = tile.eval(&sm, A.L, net_input(A.L, x, y, z, tt, cx, cy), c);
+    const float gx = quad_bcast<1>(val), gy = quad_bcast<2>(val), gz = quad_bcast<3>(val);
+    if (c == 0 && g == 0 && ray >= 0) {
+      float fx = A.L.amplitude * gx, fy = A.L.amplitude * gy, fz = A.L.amplitude * gz;
+      if (A.B.sphere) {
+        const float dx = x - cx, dy = y - cy;
+        const float r = sqrtf(fmaf(dx, dx, fmaf(dy, dy, z * z)));
+        if (r > 0.f) {
+          fx += dx / r;
+          fy += dy / r;
+          fz += z / r;
+        }
+      }
+      const float len = sqrtf(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
+      const float inv = len > 0.f ? 1.f / len : 0.f;
+      A.normal[3 * ray + 0] = fx * inv;
+      A.normal[3 * ray + 1] = fy * inv;
+      A.normal[3 * ray + 2] = fz * inv;
+    }
+  }
+}
+
+// Value and raw gradient at points (analytic_normal / nnm_net_eval).
+template <int H, int P>
+__global__ void __launch_bounds__(kBlockThreads) k_points(PointsArgs A) {
+  __shared__ NetSmem<H> sm;
+  stage_net<H>(&sm, A.L);
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 31;
+  const int g = lane >> 5;
+  const int q = col >> 2, c = col & 3;
+  const int waves = kBlockThreads / 64;
+  const int wave = blockIdx.x * waves + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * waves;
+  SirenTile<H, P, true> tile;
+  for (int base = wave * 8; base < A.n; base += nwaves * 8) {
+    const int i = base + q;
+    const bool live = i < A.n;
+    float x = 0.f, y = 0.f, z = 0.f, tt = 0.f;
+    if (live) {
+      x = A.x[3 * i + 0];
+      y = A.x[3 * i + 1];
+      z = A.x[3 * i + 2];
+      tt = A.t ? A.t[i] : 0.f;
+    }
+    float cx, cy;
+    center_at(A.B, tt, cx, cy);
+    const float val = tile.eval(&sm, A.L, net_input(A.L, x, y, z, tt, cx, cy), c);
+    const float gx = quad_bcast<1>(val), gy = quad_bcast<2>(val), gz = quad_bcast<3>(val);
+    if (c == 0 && g == 0 && live) {
+      if (A.raw) {
+        if (A.value) A.value[i] = val;
+        if (A.grad) {
+          A.grad[3 * i + 0] = gx;
+          A.grad[3 * i + 1] = gy;
+          A.grad[3 * i + 2] = gz;
+        }
+      } else {
+        float f = A.L.amplitude * val;
+        float fx = A.L.amplitude * gx, fy = A.L.amplitude * gy, fz = A.L.amplitude * gz;
+        if (A.B.sphere) {
+          const float dx = x - cx, dy = y - cy;
+          const float r = sqrtf(fmaf(dx, dx, fmaf(dy, dy, z * z)));
+          f = fmaf(A.L.amplitude, val, r - A.B.r0);
+          if (r > 0.f) {
+            fx += dx / r;
+            fy += dy / r;
+            fz += z / r;
+          }
+        }
+        if (A.value) A.value[i] = f;
+        if (A.grad) {
+          A.grad[3 * i + 0] = fx;
+          A.grad[3 * i + 1] = fy;
+          A.grad[3 * i + 2] = fz;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_zero_ints(int* p, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_ints, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+
+#define NNM_DISPATCH(WIDTH, PREC, CALL)                                   \
+  switch ((WIDTH) * 4 + (PREC)) {                                         \
+    case 32 * 4 + PREC_FP32: { CALL(32, PREC_FP32); } break;              \
+    case 32 * 4 + PREC_BF16: { CALL(32, PREC_BF16); } break;              \
+    case 32 * 4 + PREC_FP16: { CALL(32, PREC_FP16); } break;              \
+    case 64 * 4 + PREC_FP32: { CALL(64, PREC_FP32); } break;              \
+    case 64 * 4 + PREC_BF16: { CALL(64, PREC_BF16); } break;              \
+    case 64 * 4 + PREC_FP16: { CALL(64, PREC_FP16); } break;              \
+    case 128 * 4 + PREC_FP32: { CALL(128, PREC_FP32); } break;            \
+    case 128 * 4 + PREC_BF16: { CALL(128, PREC_BF16); } break;            \
+    case 128 * 4 + PREC_FP16: { CALL(128, PREC_FP16); } break;            \
+    case 256 * 4 + PREC_FP32: { CALL(256, PREC_FP32); } break;            \
+    case 256 * 4 + PREC_BF16: { CALL(256, PREC_BF16); } break;            \
+    case 256 * 4 + PREC_FP16: { CALL(256, PREC_FP16); } break;            \
+    default: return hipErrorInvalidValue;                                 \
+  }
+
+hipError_t launch_trace_level(int width, int prec, const TraceLevelArgs& a, int grid, hipStream_t s) {
+#define CALL(H, P) hipLaunchKernelGGL((k_trace_level<H, P>), dim3(grid), dim3(kBlockThreads), 0, s, a)
+  NNM_DISPATCH(width, prec, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_normal(int width, int prec, const NormalArgs& a, int grid, hipStream_t s) {
+#define CALL(H, P) hipLaunchKernelGGL((k_normal<H, P>), dim3(grid), dim3(kBlockThreads), 0, s, a)
+  NNM_DISPATCH(width, prec, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_points(int width, int prec, const PointsArgs& a, int grid, hipStream_t s) {
+#define CALL(H, P) hipLaunchKernelGGL((k_points<H, P>), dim3(grid), dim3(kBlockThreads), 0, s, a)
+  NNM_DISPATCH(width, prec, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+static int occupancy_of(const void* fn, int device) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlockThreads, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
+  return per_cu * cus;
+}
+
+int resident_blocks(int width, int prec, int kind, int device) {
+  int out = 0;
+#define CALL(H, P)                                                                              \
+  {                                                                                             \
+    const void* fn = kind == 0 ? (const void*)k_trace_level<H, P>                               \
+                               : (kind == 1 ? (const void*)k_normal<H, P> : (const void*)k_points<H, P>); \
+    out = occupancy_of(fn, device);                                                             \
+  }
+  switch (width * 4 + prec) {
+    case 32 * 4 + PREC_FP32: CALL(32, PREC_FP32); break;
+    case 32 * 4 + PREC_BF16: CALL(32, PREC_BF16); break;
+    case 32 * 4 + PREC_FP16: CALL(32, PREC_FP16); break;
+    case 64 * 4 + PREC_FP32: CALL(64, PREC_FP32); break;
+    case 64 * 4 + PREC_BF16: CALL(64, PREC_BF16); break;
+    case 64 * 4 + PREC_FP16: CALL(64, PREC_FP16); break;
+    case 128 * 4 + PREC_FP32: CALL(128, PREC_FP32); break;
+    case 128 * 4 + PREC_BF16: CALL(128, PREC_BF16); break;
+    case 128 * 4 + PREC_FP16: CALL(128, PREC_FP16); break;
+    case 256 * 4 + PREC_FP32: CALL(256, PREC_FP32); break;
+    case 256 * 4 + PREC_BF16: CALL(256, PREC_BF16); break;
+    case 256 * 4 + PREC_FP16: CALL(256, PREC_FP16); break;
+    default: out = 1;
+  }
+#undef CALL
+  return out;
+}
+
+}  // namespace nnm

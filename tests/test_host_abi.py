@@ -1,0 +1,128 @@
+"""Host-only checks of libnnm (no GPU needed): the library loads and exports
+every function include/nnm.h declares; descriptor validation maps each bad
+input to its error code before any device use; the network-file parser; the
+Lipschitz product bound against numpy's SVD; the binding fails loudly."""
+
+import os
+import re
+import struct
+
+import numpy as np
+import pytest
+
+import nnm_inputs as ni
+import paper_2201_09147_amd as nnm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nnm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(nnm.library_path()):
+        from paper_2201_09147_amd import build as b
+        b.build()
+    return nnm.load_library()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared_functions()
+    assert {"load_siren_stack", "trace_rays", "analytic_normal", "free_siren_stack",
+            "nnm_last_error"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _levels():
+    return nnm.levels_from_scene(ni.make_scene("stack3_512sq"))
+
+
+def test_validate_accepts_workload_scenes(lib):
+    for name in ["single_64x1_128sq", "stack3_512sq", "anim16_1024sq"]:
+        s = ni.make_scene(name)
+        for prec in ("fp32", "bf16", "fp16"):
+            assert nnm.nnm_validate_stack(nnm.levels_from_scene(s), prec, s.base_sphere, s.r0, s.rho) == 0
+
+
+def test_validate_error_paths(lib):
+    lv = _levels()
+    E = {"INVAL": -1, "FORMAT": -2, "NONFINITE": -3, "LIPSCHITZ": -4, "NESTING": -5, "UNSUPPORTED": -8}
+    assert nnm.nnm_validate_stack([], "fp32") == E["INVAL"]
+    bad = [nnm.LevelSpec(l.d_in, l.width, l.n_sine, l.params.copy(), l.amplitude, l.delta) for l in lv]
+    bad[1].params[17] = np.nan
+    assert nnm.nnm_validate_stack(bad, "fp32") == E["NONFINITE"]
+    bad = list(lv)
+    bad[0] = nnm.LevelSpec(3, 48, 2, lv[0].params, 0.005, 0.05)
+    assert nnm.nnm_validate_stack(bad, "fp32") == E["UNSUPPORTED"]
+    bad[0] = nnm.LevelSpec(5, 32, 2, lv[0].params, 0.005, 0.05)
+    assert nnm.nnm_validate_stack(bad, "fp32") == E["UNSUPPORTED"]
+    assert nnm.nnm_validate_stack(lv, 7) == E["UNSUPPORTED"]
+    # deltas must decrease and stay positive on all but the last level
+    bad = [nnm.LevelSpec(l.d_in, l.width, l.n_sine, l.params, l.amplitude, d)
+           for l, d in zip(lv, [0.01, 0.05, 0.0])]
+    assert nnm.nnm_validate_stack(bad, "fp32") == E["NESTING"]
+    bad = [nnm.LevelSpec(l.d_in, l.width, l.n_sine, l.params, l.amplitude, d)
+           for l, d in zip(lv, [0.05, 0.0, 0.0])]
+    assert nnm.nnm_validate_stack(bad, "fp32") == E["NESTING"]
+    # a larger amplitude breaks the Lipschitz bound; lipschitz_max = 0 disables the check
+    bad = [nnm.LevelSpec(l.d_in, l.width, l.n_sine, l.params, l.amplitude * 3, l.delta) for l in lv]
+    assert nnm.nnm_validate_stack(bad, "fp32") == E["LIPSCHITZ"]
+    assert nnm.nnm_validate_stack(bad, "fp32", lipschitz_max=0.0) == 0
+    bad = [nnm.LevelSpec(l.d_in, l.width, l.n_sine, l.params, float("inf"), l.delta) for l in lv]
+    assert nnm.nnm_validate_stack(bad, "fp32") == E["NONFINITE"]
+    assert "amplitude" in lib.nnm_last_error().decode()
+
+
+def test_lipschitz_bound_matches_svd(lib):
+    for l in ni.make_scene("stack3_512sq").levels:
+        spec = nnm.levels_from_scene(type("S", (), {"levels": [l]})())[0]
+        b = nnm.nnm_level_lipschitz_bound(spec, True)
+        ref = 1.0 + l.amplitude * ni.lipschitz_product_bound(l.net.layers)
+        assert abs(b - ref) <= 1e-9 * ref
+
+
+def test_net_file_roundtrip_and_errors(lib, tmp_path):
+    net = ni.siren_init(2, 3, 64, 2, 0.015)
+    p = tmp_path / "net.nnmw"
+    ni.write_net_file(p, net)
+    d_in, width, n_sine, params = nnm.nnm_read_net_file(str(p))
+    assert (d_in, width, n_sine) == (3, 64, 2)
+    assert np.array_equal(params, net.flat())
+    assert lib.nnm_param_count(3, 256, 3) == 132865
+    raw = p.read_bytes()
+    (tmp_path / "magic.nnmw").write_bytes(b"XXXX" + raw[4:])
+    (tmp_path / "short.nnmw").write_bytes(raw[:-8])
+    (tmp_path / "long.nnmw").write_bytes(raw + b"\0\0\0\0")
+    (tmp_path / "shape.nnmw").write_bytes(raw[:8] + struct.pack("<I", 7) + raw[12:])
+    for name in ("magic", "short", "long", "shape"):
+        with pytest.raises(nnm.NnmError) as e:
+            nnm.nnm_read_net_file(str(tmp_path / f"{name}.nnmw"))
+        assert e.value.code == -2, name
+    with pytest.raises(nnm.NnmError) as e:
+        nnm.nnm_read_net_file(str(tmp_path / "missing.nnmw"))
+    assert e.value.code == -9
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2201_09147_amd import _binding
+    monkeypatch.setattr(_binding, "_lib", None)
+    monkeypatch.setattr(_binding, "_LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(nnm.NnmError):
+        _binding.load_library()
+
+
+def test_product_path_does_not_reference_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2201_09147_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower(), f
