@@ -9,7 +9,8 @@ from typing import List, Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libnnm.so")
+# NNM_LIBRARY selects another build of the same library (e.g. a tuning variant).
+_LIB_PATH = os.environ.get("NNM_LIBRARY") or os.path.join(_HERE, "libnnm.so")
 
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 ST_HIT, ST_FAR, ST_BUDGET, ST_NEG_STEP, ST_NONFINITE = 1, 2, 4, 8, 16

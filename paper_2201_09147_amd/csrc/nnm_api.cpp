@@ -459,8 +459,11 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
   const int L = p->final_level + 1;
   // Scratch: counters (head and out count per level), two ping-pong queues,
   // and the status carrier when the caller passes none.
+  // cnt[2j], cnt[2j+1]: spare / rays out of level j; heads of level j at
+  // cnt + 64 + j * kSegments * kHeadStride.
+  const int n_cnt = 64 + kMaxLevels * kSegments * kHeadStride;
   const size_t off_cnt = 0;
-  const size_t off_qa = 256;
+  const size_t off_qa = align256((size_t)n_cnt * 4);
   const size_t off_qb = off_qa + align256((size_t)n * 4);
   const size_t off_st = off_qb + align256((size_t)n * 4);
   const size_t total = off_st + (status ? 0 : align256((size_t)n));
@@ -468,11 +471,12 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
   hipError_t e = hipMallocAsync(&ws, total, st);
   if (e != hipSuccess) return fail(NNM_E_NOMEM, "hipMallocAsync(%zu): %s", total, hipGetErrorString(e));
   char* wb = (char*)ws;
-  int* cnt = (int*)(wb + off_cnt);  // cnt[2j]: pop head of level j, cnt[2j+1]: rays out of level j
+  int* cnt = (int*)(wb + off_cnt);
   int* q[2] = {(int*)(wb + off_qa), (int*)(wb + off_qb)};
   uint8_t* stat = status ? status : (uint8_t*)(wb + off_st);
   int rc = NNM_OK;
-  if ((e = launch_zero_ints(cnt, 64, st)) != hipSuccess) rc = hip_fail(e, "zeroing counters");
+  if ((e = launch_zero_ints(cnt, 64 + L * kSegments * kHeadStride, st)) != hipSuccess)
+    rc = hip_fail(e, "zeroing counters");
   for (int j = 0; j < L && rc == NNM_OK; ++j) {
     const auto& lv = s->levels[j];
     TraceLevelArgs a{};
@@ -488,7 +492,7 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
     a.status = stat;
     a.in_queue = j == 0 ? nullptr : q[(j - 1) & 1];
     a.in_count = j == 0 ? nullptr : cnt + 2 * (j - 1) + 1;
-    a.in_head = cnt + 2 * j;
+    a.in_heads = cnt + 64 + j * kSegments * kHeadStride;
     const bool is_final = (j == L - 1);
     a.out_queue = (!is_final || normal) ? q[j & 1] : nullptr;
     a.out_count = cnt + 2 * j + 1;

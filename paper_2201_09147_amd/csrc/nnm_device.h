@@ -27,6 +27,10 @@ constexpr int kMaxLevels = 8;
 constexpr int kMaxSine = 8;
 constexpr int kWaveCols = 32;       // columns per wave tile
 constexpr int kBlockThreads = 256;  // 4 waves per workgroup
+constexpr int kChunk = 256;         // most queue entries a wave takes per atomic
+constexpr int kPushBatch = 64;      // queue entries a wave publishes per atomic
+constexpr int kSegments = 64;       // input queue segments, each with its own head
+constexpr int kHeadStride = 32;     // ints between segment heads (one 128-byte line each)
 
 // Index of the accumulator-layout slot (mb, g, r) in a [H] array.
 __host__ __device__ inline int acc_slot(int mb, int g, int r) { return (mb * 2 + g) * 16 + r; }
@@ -53,7 +57,8 @@ struct DevLevel {
   const float* wk;    // [H] acc layout: output weights (unscaled)
   const void* ah;     // packed MFMA A fragments of the hidden layers
   long long ah_stride;  // bytes per hidden layer of `ah`
-  float bk;           // output bias
+  float bk;           // output bias (used when bk_dev is null)
+  const float* bk_dev;  // device copy of the output bias, or null
   float amplitude;
   float delta;
   int d_in;

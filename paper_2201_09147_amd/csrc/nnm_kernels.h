@@ -24,7 +24,7 @@ struct TraceLevelArgs {
   uint8_t* status;      // never null (library scratch when the caller passes null)
   const int* in_queue;  // null: ray ids 0..n-1
   const int* in_count;  // null: n
-  int* in_head;         // pop counter
+  int* in_heads;        // kSegments pop counters, kHeadStride ints apart, zeroed
   int* out_queue;       // rays that finished this level (next level / hits); may be null
   int* out_count;
   int n;
@@ -63,6 +63,62 @@ struct PointsArgs {
   int n;
   int raw;  // 1: the network N alone; 0: the scene function f
 };
+
+// Device packing of flat float32 parameters for the fitting kernels.
+struct FitPackArgs {
+  const float* params;
+  int d_in, width, n_sine;
+  long long w_off[kMaxSine + 1];
+  long long b_off[kMaxSine + 1];
+  float* a0;    // [3][H/32][64] layer-0 A operand / 2pi
+  float* bh;    // [(K-1) H] hidden biases / 2pi, accumulator layout
+  float* wk;    // [H] output weights, accumulator layout
+  float* ah;    // [(K-1)][H*H] hidden W / 2pi, fp32 32x32x2 fragments
+  float* aht;   // [(K-1)][H*H] hidden W^T (unscaled), same fragment layout
+  float4* w0t;  // [H] W_0 rows (unscaled), accumulator layout
+  float* bk;    // [1] output bias
+};
+
+// Fused forward + adjoint + reverse over a batch of points.
+struct FitArgs {
+  DevLevel L;
+  const float* aht;
+  const float4* w0t;
+  int n;        // points
+  int n_surf;   // loss mode: points [0, n_surf) are surface samples
+  int mode;     // 0: eikonal fitting loss, 1: upstream adjoints
+  const float* x0;  // loss: surface points [n_surf][3]; upstream: all points [n][d_in]
+  const float* x1;  // loss: uniform points [n - n_surf][3]
+  const float* surf_n;
+  const float* unif_sdf;
+  const float* dvalue;  // upstream dL/dN [n] or null
+  const float* dgrad;   // upstream dL/d grad N [n][3] or null
+  float inv_ns, inv_nu;
+  float* ws_abar;  // [K][H][Kc]: pre-activations, then [abar | dAbar]
+  float* ws_x;     // [K][H][Kc]: inputs of layers 1..K
+  float* adj;      // [Kc]: dL/dN or dL/d grad N per column
+  float* loss_part;  // [waves][4] or null
+  float* dx;         // [n][d_in] or null
+  long long Kc;      // 4 columns per point, 32 per tile of 8 points
+};
+
+struct FitVecArgs {
+  long long Kc;
+  int n, n_surf, mode, d_in;
+  const float* x0;
+  const float* x1;
+  float* mask;  // [Kc] 1 on primal columns of live points
+  float* wvec;  // [d_in][Kc] column weights of the layer-0 gradient
+};
+
+hipError_t launch_fit_pack(const FitPackArgs& a, hipStream_t s);
+hipError_t launch_fit_fb(const FitArgs& a, int grid, hipStream_t s);
+hipError_t launch_fit_vectors(const FitVecArgs& a, hipStream_t s);
+hipError_t launch_fit_loss_reduce(const float* part, int nwaves, float inv_ns, float inv_nu, float* loss4,
+                                  hipStream_t s);
+hipError_t launch_adam(float* params, const float* grad, float* m, float* v, long long n, float lr, float b1,
+                       float b2, float eps, float bc1, float bc2, hipStream_t s);
+int fit_fb_grid(int width, int device);
 
 hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
 hipError_t launch_trace_level(int width, int prec, const TraceLevelArgs& a, int grid, hipStream_t s);

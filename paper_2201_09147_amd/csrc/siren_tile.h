@@ -36,6 +36,15 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr float kTwoPi = 6.28318530717958647692f;
 
+// Depth (in k-steps) of the register ring that prefetches hidden-layer A
+// fragments from L2.
+#ifndef NNM_RING_FP32
+#define NNM_RING_FP32 2
+#endif
+#ifndef NNM_RING_LOWP
+#define NNM_RING_LOWP 4
+#endif
+
 // Compiler barrier: memory operations are not moved across it, which keeps
 // loop-invariant table reads from being hoisted into long-lived registers.
 #define NNM_MEM_FENCE() __asm__ volatile("" ::: "memory")
@@ -108,6 +117,38 @@ __device__ inline float layer0_input(float4 in, int d_in, int c, int ks, int g) 
   return k == 3 ? 1.f : 0.f;
 }
 
+// acc += A b over an H x H layer with 32x32x2 fp32 MFMAs: k-step ks uses
+// b[ks/16][ks%16] (accumulator layout of the previous layer); A packed as
+// f32x4 groups of four k-steps, streamed through a register ring.
+template <int H>
+__device__ inline void gemm_fp32(const float (&b)[H / 32][16], const f32x4_t* A, f32x16_t* acc) {
+  constexpr int MB = H / 32;
+  constexpr int NQ = H / 8;
+  constexpr int kRing = NNM_RING_FP32;
+  const int lane = threadIdx.x & 63;
+  f32x4_t ring[kRing][MB];
+#pragma unroll
+  for (int d = 0; d < kRing; ++d)
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) ring[d][mb] = A[(d * MB + mb) * 64 + lane];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ks = 4 * q + e;
+      const float bv = b[ks / 16][ks % 16];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+        acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ring[q % kRing][mb][e], bv, acc[mb], 0, 0, 0);
+    }
+    if (q + kRing < NQ) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) ring[q % kRing][mb] = A[((q + kRing) * MB + mb) * 64 + lane];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 template <int H, int P, bool TAN>
 struct SirenTile {
   static constexpr int MB = H / 32;
@@ -133,11 +174,11 @@ struct SirenTile {
       }
   }
 
-  __device__ inline void first_layer(const DevLevel& L, float4 in, int c) {
+  // Layer-0 accumulators: W_0 [in | 1] / 2 pi (tangent columns: W_0[:, c-1] / 2 pi).
+  __device__ inline void layer0_acc(const DevLevel& L, float4 in, int c, f32x16_t* acc) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 5;
     const int ks0 = L.d_in == 4 ? 3 : 2;
-    f32x16_t acc[MB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -152,54 +193,33 @@ struct SirenTile {
           acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[(ks * MB + mb) * 64 + lane], b, acc[mb], 0, 0, 0);
       }
     }
+  }
+
+  __device__ inline void first_layer(const DevLevel& L, float4 in, int c) {
+    f32x16_t acc[MB];
+    layer0_acc(L, in, c, acc);
     activate(acc, c, true);
   }
 
-  __device__ inline void hidden_layer(const NetSmem<H>* sm, const DevLevel& L, int layer, int c) {
+  // Hidden-layer accumulators W_i act / 2 pi + b_i / 2 pi (bias on primal columns).
+  __device__ inline void hidden_acc(const NetSmem<H>* sm, const DevLevel& L, int layer, int c, f32x16_t* acc) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 5;
     NNM_MEM_FENCE();
     const float* bias = sm->bh + (layer - 1) * H;
     // C = bias for primal columns; tangent columns carry W G only.
     const bool primal = !TAN || c == 0;
-    f32x16_t acc[MB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[mb][r] = primal ? bias[acc_slot(mb, g, r)] : 0.f;
     const char* base = (const char*)L.ah + (long long)(layer - 1) * L.ah_stride;
-    // A fragments stream from L2 through a ring of kRing k-steps; scheduling
-    // barriers keep the compiler from issuing a whole layer of loads at once.
-    constexpr int kRing = 2;
     if constexpr (P == PREC_FP32) {
-      // 32x32x2 fp32: k-step ks uses activation act[ks/16][ks%16]; four k-steps
-      // per 16-byte A load (group q).
-      constexpr int NQ = H / 8;
-      const f32x4_t* A = (const f32x4_t*)base;
-      f32x4_t ring[kRing][MB];
-#pragma unroll
-      for (int d = 0; d < kRing; ++d)
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) ring[d][mb] = A[(d * MB + mb) * 64 + lane];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int ks = 4 * q + e;
-          const float b = act[ks / 16][ks % 16];
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-            acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ring[q % kRing][mb][e], b, acc[mb], 0, 0, 0);
-        }
-        if (q + kRing < NQ) {
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb) ring[q % kRing][mb] = A[((q + kRing) * MB + mb) * 64 + lane];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      gemm_fp32<H>(act, (const f32x4_t*)base, acc);
     } else {
       typedef HiddenOps<P> Ops;
       typedef typename Ops::frag_t frag_t;
+      constexpr int kRing = NNM_RING_LOWP;
       constexpr int KS = 2 * MB;
       frag_t bfr[KS];
 #pragma unroll
@@ -224,17 +244,18 @@ struct SirenTile {
         __builtin_amdgcn_sched_barrier(0);
       }
     }
+  }
+
+  __device__ inline void hidden_layer(const NetSmem<H>* sm, const DevLevel& L, int layer, int c) {
+    f32x16_t acc[MB];
+    hidden_acc(sm, L, layer, c, acc);
     activate(acc, c, L.reduce_hidden != 0);
   }
 
-  // Returns, per lane, the output of its column after the cross-half reduction:
-  // forward mode N (same on both halves); tangent mode N for c == 0 and
-  // dN/dx_{c-1} for c = 1..3.
-  __device__ inline float eval(const NetSmem<H>* sm, const DevLevel& L, float4 in, int c) {
+  // Output layer on the current activations: per lane, the reduced value of
+  // its column (N for primal columns, dN/dx_{c-1} for tangent columns).
+  __device__ inline float output(const NetSmem<H>* sm, const DevLevel& L, int c) {
     const int g = (threadIdx.x & 63) >> 5;
-    NNM_MEM_FENCE();
-    first_layer(L, in, c);
-    for (int layer = 1; layer < L.n_sine; ++layer) hidden_layer(sm, L, layer, c);
     NNM_MEM_FENCE();
     float part = 0.f;
 #pragma unroll
@@ -244,8 +265,18 @@ struct SirenTile {
       __builtin_amdgcn_sched_barrier(0);
     }
     part += __shfl_xor(part, 32);
-    if (!TAN || c == 0) part += L.bk;
+    if (!TAN || c == 0) part += L.bk_dev ? *L.bk_dev : L.bk;
     return part;
+  }
+
+  // Returns, per lane, the output of its column after the cross-half reduction:
+  // forward mode N (same on both halves); tangent mode N for c == 0 and
+  // dN/dx_{c-1} for c = 1..3.
+  __device__ inline float eval(const NetSmem<H>* sm, const DevLevel& L, float4 in, int c) {
+    NNM_MEM_FENCE();
+    first_layer(L, in, c);
+    for (int layer = 1; layer < L.n_sine; ++layer) hidden_layer(sm, L, layer, c);
+    return output(sm, L, c);
   }
 };
 

@@ -40,52 +40,84 @@ __global__ void k_zero_ints(int* p, int count) {
 template <int H, int P>
 __global__ void __launch_bounds__(kBlockThreads) k_trace_level(TraceLevelArgs A) {
   __shared__ NetSmem<H> sm;
+  // Per-wave ring of rays that finished the level, flushed to the output queue
+  // kPushBatch at a time (one atomic per batch, coalesced stores).
+  __shared__ int push_ring[kBlockThreads / 64][2 * kPushBatch];
   stage_net<H>(&sm, A.L);
   const int lane = threadIdx.x & 63;
   const int col = lane & 31;
   const int g = lane >> 5;
+  int* ring = push_ring[threadIdx.x >> 6];
   const int n_in = A.in_count ? *A.in_count : A.n;
   SirenTile<H, P, false> tile;
   int ray = -1, k = 0, st = 0;
   float tau = 0.f, ox = 0.f, oy = 0.f, oz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, tt = 0.f;
+  // Wave-uniform work chunk [cur, end) of the input queue and push-ring state.
+  // The queue is split into kSegments contiguous segments with one pop counter
+  // each (separate cache lines, so the atomics spread over many addresses); a
+  // wave starts in segment (wave id mod kSegments) and moves on when it is
+  // empty.  Chunks hold about n_in / (8 * resident waves) entries (32..kChunk),
+  // so every wave takes several chunks and the queue drains evenly.
+  int cur = 0, end = 0, ring_start = 0, ring_n = 0;
+  const int nwaves = gridDim.x * (kBlockThreads / 64);
+  const int wave_id = blockIdx.x * (kBlockThreads / 64) + (threadIdx.x >> 6);
+  const int chunk = min(kChunk, max(32, (n_in / (8 * nwaves)) & ~31));
+  const int seg_len = (n_in + kSegments - 1) / kSegments;
+  int seg = wave_id % kSegments, seg_tries = 0;
   bool exhausted = false;
   for (;;) {
-    // Refill empty slots from the input queue.  Both halves of a column hold
-    // the same slot state, so the lower half's ballot describes the slots.
-    if (!exhausted) {
-      const unsigned int emask = (unsigned int)__ballot(ray < 0);
-      const int cnt = __popc(emask);
-      if (cnt > 0) {
+    // Refill empty slots from the wave's chunk, grabbing a new chunk of
+    // kChunk queue entries (one atomic) when it runs dry.  Both halves of a
+    // column hold the same slot state, so the lower half's ballot is enough.
+    unsigned int emask = (unsigned int)__ballot(ray < 0);
+    while (emask != 0u && !exhausted) {
+      if (cur >= end) {
+        const int s0 = seg * seg_len;
+        const int s_len = max(0, min(seg_len, n_in - s0));
         int base = 0;
-        if (lane == 0) base = atomicAdd(A.in_head, cnt);
+        if (lane == 0) base = atomicAdd(A.in_heads + seg * kHeadStride, chunk);
         base = __shfl(base, 0);
-        const int avail = n_in - base;
-        if (avail <= cnt) exhausted = true;
-        if (ray < 0) {
-          const int pos = __popc(emask & ((1u << col) - 1u));
-          if (pos < avail) {
-            const int idx = base + pos;
-            ray = A.in_queue ? A.in_queue[idx] : idx;
-            ox = A.o[3 * ray + 0];
-            oy = A.o[3 * ray + 1];
-            oz = A.o[3 * ray + 2];
-            vx = A.v[3 * ray + 0];
-            vy = A.v[3 * ray + 1];
-            vz = A.v[3 * ray + 2];
-            tt = A.t ? A.t[ray] : 0.f;
-            k = 0;
-            if (A.level == 0) {
-              tau = 0.f;
-              st = 0;
-              if (A.steps && g == 0)
-                for (int j = 1; j < A.m; ++j) A.steps[(long long)ray * A.m + j] = 0;
-            } else {
-              tau = A.depth[ray];
-              st = A.status[ray];
-            }
+        if (base >= s_len) {
+          // this segment is drained: try the next one
+          seg = (seg + 1) % kSegments;
+          if (++seg_tries >= kSegments) {
+            exhausted = true;
+            break;
+          }
+          continue;
+        }
+        cur = s0 + base;
+        end = s0 + min(base + chunk, s_len);
+      }
+      const int avail = end - cur;
+      const int cnt = __popc(emask);
+      const int take = min(cnt, avail);
+      if (ray < 0) {
+        const int pos = __popc(emask & ((1u << col) - 1u));
+        if (pos < take) {
+          const int idx = cur + pos;
+          ray = A.in_queue ? A.in_queue[idx] : idx;
+          ox = A.o[3 * ray + 0];
+          oy = A.o[3 * ray + 1];
+          oz = A.o[3 * ray + 2];
+          vx = A.v[3 * ray + 0];
+          vy = A.v[3 * ray + 1];
+          vz = A.v[3 * ray + 2];
+          tt = A.t ? A.t[ray] : 0.f;
+          k = 0;
+          if (A.level == 0) {
+            tau = 0.f;
+            st = 0;
+            if (A.steps && g == 0)
+              for (int j = 1; j < A.m; ++j) A.steps[(long long)ray * A.m + j] = 0;
+          } else {
+            tau = A.depth[ray];
+            st = A.status[ray];
           }
         }
       }
+      cur += take;
+      emask = (unsigned int)__ballot(ray < 0);
     }
     if (__ballot(ray >= 0) == 0ull) break;
 
@@ -121,13 +153,22 @@ __global__ void __launch_bounds__(kBlockThreads) k_trace_level(TraceLevelArgs A)
         }
       }
     }
-    // Compaction: rays that finished the level go to the output queue.
+    // Compaction: rays that finished the level enter the wave's push ring.
     const unsigned int pmask = (unsigned int)__ballot(outcome == 1);
     if (pmask && A.out_queue) {
-      int pbase = 0;
-      if (lane == 0) pbase = atomicAdd(A.out_count, __popc(pmask));
-      pbase = __shfl(pbase, 0);
-      if (outcome == 1 && g == 0) A.out_queue[pbase + __popc(pmask & ((1u << col) - 1u))] = ray;
+      if (outcome == 1 && g == 0)
+        ring[(ring_start + ring_n + __popc(pmask & ((1u << col) - 1u))) & (2 * kPushBatch - 1)] = ray;
+      ring_n += __popc(pmask);
+      if (ring_n >= kPushBatch) {
+        __builtin_amdgcn_wave_barrier();
+        int base = 0;
+        if (lane == 0) base = atomicAdd(A.out_count, kPushBatch);
+        base = __shfl(base, 0);
+        if (lane < kPushBatch) A.out_queue[base + lane] = ring[(ring_start + lane) & (2 * kPushBatch - 1)];
+        __builtin_amdgcn_wave_barrier();
+        ring_start = (ring_start + kPushBatch) & (2 * kPushBatch - 1);
+        ring_n -= kPushBatch;
+      }
     }
     if (outcome != 0) {
       if (g == 0) {
@@ -152,6 +193,14 @@ __global__ void __launch_bounds__(kBlockThreads) k_trace_level(TraceLevelArgs A)
       }
       ray = -1;
     }
+  }
+  // Flush what is left in the push ring.
+  if (ring_n > 0 && A.out_queue) {
+    __builtin_amdgcn_wave_barrier();
+    int base = 0;
+    if (lane == 0) base = atomicAdd(A.out_count, ring_n);
+    base = __shfl(base, 0);
+    if (lane < ring_n) A.out_queue[base + lane] = ring[(ring_start + lane) & (2 * kPushBatch - 1)];
   }
 }
 
