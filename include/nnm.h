@@ -164,6 +164,85 @@ int analytic_normal(const nnm_stack* stack, int level, int64_t n, const float* x
 int nnm_net_eval(const nnm_stack* stack, int level, int64_t n, const float* x, const float* t,
                  float* value, float* grad, void* stream);
 
+/* ---------------------------------------------------------------- fitting */
+
+/* Differentiation of one SIREN N (Eq.(2)) with respect to its parameters,
+   through the value and the analytic gradient (a double backward), in
+   float32.  `params` is the flat float32 parameter vector in nnm_level_desc
+   order; `d_in` 3 or 4 (the gradient is w.r.t. the first three inputs), width
+   32 / 64 / 128 / 256, 1 .. 8 sine layers. */
+typedef struct {
+  int32_t d_in;
+  int32_t width;
+  int32_t n_sine;
+  int32_t reserved;
+} nnm_net_shape;
+
+/* Bytes of device workspace that siren_backward needs for n points. */
+int64_t siren_workspace_bytes(const nnm_net_shape* shape, int64_t n);
+
+/* Forward with tangents: value[n] = N(x), grad[n][3] = grad_x N (either may
+   be NULL).  params, x: device.  No workspace; asynchronous on `stream`. */
+int siren_forward_tangent(const nnm_net_shape* shape, const float* params, int64_t n, const float* x,
+                          float* value, float* grad, void* stream);
+
+/* Reverse mode through primal and tangent: given upstream adjoints
+   dvalue[n] (= dL/dN, may be NULL for 0) and dgrad[n][3] (= dL/d grad N, may be
+   NULL for 0), writes dparams[P] (= dL/dparams, overwritten) and, if dx is not
+   NULL, dx[n][d_in] (= dL/dx through N only).  The forward is recomputed; the
+   workspace (device, >= siren_workspace_bytes) holds per-layer values for the
+   weight-gradient products.  All pointers device; asynchronous on `stream`. */
+int siren_backward(const nnm_net_shape* shape, const float* params, int64_t n, const float* x,
+                   const float* dvalue, const float* dgrad, float* dparams, float* dx, void* workspace,
+                   int64_t workspace_bytes, void* stream);
+
+/* A fitting state: parameters, Adam moments and step counter on one device,
+   with the workspace for up to max_points points per step. */
+typedef struct nnm_fit nnm_fit;
+
+/* One batch of the eikonal fitting loss (device pointers):
+     L = mean_surf |N| + mean_surf (1 - n . grad N)
+       + mean_unif |N - sdf| + mean_unif (|grad N| - 1)^2  */
+typedef struct {
+  int64_t n_surf;
+  int64_t n_unif;
+  const float* surf_x;   /* [n_surf][3] points on the surface */
+  const float* surf_n;   /* [n_surf][3] unit normals there */
+  const float* unif_x;   /* [n_unif][3] points in the domain */
+  const float* unif_sdf; /* [n_unif] signed distances there */
+} nnm_fit_batch;
+
+/* Adam (Kingma & Ba, bias corrected, no weight decay). */
+typedef struct {
+  float lr;
+  float beta1;
+  float beta2;
+  float eps;
+} nnm_adam;
+
+/* Creates a fitting state from host float32 parameters (copied). */
+int fit_create(const nnm_net_shape* shape, const float* params, int device, int64_t max_points, nnm_fit** out);
+void fit_free(nnm_fit* fit);
+
+/* One step: loss, gradient through the double backward, Adam update.  loss4:
+   device [4] out (the four mean terms), or NULL.  Asynchronous on `stream`. */
+int fit_step(nnm_fit* fit, const nnm_fit_batch* batch, const nnm_adam* opt, float* loss4, void* stream);
+
+/* Loss terms and gradient only (no update): dparams device [P] out. */
+int fit_loss_grad(nnm_fit* fit, const nnm_fit_batch* batch, float* loss4, float* dparams, void* stream);
+
+/* Device pointers of the state (owned by the fit; valid until fit_free):
+   params, Adam first and second moments, each [P] float32. */
+int fit_state(nnm_fit* fit, float** params, float** adam_m, float** adam_v, int64_t* n_params);
+/* Copies params, Adam m and v to host arrays of n_params floats (any may be
+   NULL); synchronises the device.  A checkpoint together with fit_get_step. */
+int fit_read_state(nnm_fit* fit, float* params, float* adam_m, float* adam_v);
+/* Overwrites params, m, v from host arrays (any may be NULL); synchronous. */
+int fit_write_state(nnm_fit* fit, const float* params, const float* adam_m, const float* adam_v);
+/* Steps taken so far (Adam's t); settable for a resumed run. */
+int64_t fit_get_step(const nnm_fit* fit);
+int fit_set_step(nnm_fit* fit, int64_t step);
+
 /* -------------------------------------------------------------- profiling */
 
 /* A profiler records a HIP event pair around every kernel that trace_rays

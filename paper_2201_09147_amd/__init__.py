@@ -9,7 +9,9 @@ streams (default: the current stream).
 Entry points (same names as the C ABI in include/nnm.h):
   load_siren_stack, free_siren_stack, trace_rays, analytic_normal,
   nnm_net_eval, nnm_validate_stack, nnm_read_net_file, nnm_sync
-plus ``render`` (allocates outputs and calls trace_rays).
+plus ``render`` (allocates outputs and calls trace_rays), the fitting entry
+points (``Fit`` over fit_create / fit_step, siren_forward_tangent,
+siren_backward) and ``paper_2201_09147_amd.autograd.SirenFn``.
 """
 
 from ._binding import (  # noqa: F401
@@ -37,4 +39,8 @@ from ._binding import (  # noqa: F401
     nnm_sync,
     render,
     levels_from_scene,
+    Fit,
+    siren_workspace_bytes,
+    siren_forward_tangent,
+    siren_backward,
 )

@@ -81,6 +81,18 @@ def load_library():
         "nnm_sync": ([P], c_int),
         "nnm_last_error": ([], ctypes.c_char_p),
         "nnm_version": ([], ctypes.c_char_p),
+        "siren_workspace_bytes": ([P, c_int64], c_int64),
+        "siren_forward_tangent": ([P, P, c_int64, P, P, P, P], c_int),
+        "siren_backward": ([P, P, c_int64, P, P, P, P, P, P, c_int64, P], c_int),
+        "fit_create": ([P, P, c_int, c_int64, P], c_int),
+        "fit_free": ([P], None),
+        "fit_step": ([P, P, P, P, P], c_int),
+        "fit_loss_grad": ([P, P, P, P, P], c_int),
+        "fit_state": ([P, P, P, P, P], c_int),
+        "fit_get_step": ([P], c_int64),
+        "fit_read_state": ([P, P, P, P], c_int),
+        "fit_write_state": ([P, P, P, P], c_int),
+        "fit_set_step": ([P, c_int64], c_int),
         "nnm_profiler_create": ([P], c_int),
         "nnm_profiler_free": ([P], None),
         "nnm_profiler_reset": ([P], c_int),
@@ -374,3 +386,147 @@ def render(stack: Stack, o, v, t=None, params: Optional[TraceParams] = None, wan
     trace_rays(stack, params, o, v, t, out["depth"], out["hit"], out["normal"], out["steps"], out["status"],
                stream)
     return out
+
+
+# ------------------------------------------------------------------ fitting
+
+class _NetShape(ctypes.Structure):
+    _fields_ = [("d_in", c_int32), ("width", c_int32), ("n_sine", c_int32), ("reserved", c_int32)]
+
+
+class _FitBatch(ctypes.Structure):
+    _fields_ = [("n_surf", c_int64), ("n_unif", c_int64), ("surf_x", c_void_p), ("surf_n", c_void_p),
+                ("unif_x", c_void_p), ("unif_sdf", c_void_p)]
+
+
+class _Adam(ctypes.Structure):
+    _fields_ = [("lr", c_float), ("beta1", c_float), ("beta2", c_float), ("eps", c_float)]
+
+
+def _shape(d_in, width, n_sine):
+    return _NetShape(int(d_in), int(width), int(n_sine), 0)
+
+
+def _byref(x):
+    return ctypes.cast(ctypes.byref(x), c_void_p)
+
+
+def siren_workspace_bytes(d_in, width, n_sine, n) -> int:
+    sh = _shape(d_in, width, n_sine)
+    return int(load_library().siren_workspace_bytes(_byref(sh), int(n)))
+
+
+def siren_forward_tangent(d_in, width, n_sine, params, x, value=None, grad=None, stream=None):
+    """N(x) and grad_x N for a flat float32 parameter vector (device tensors)."""
+    import torch
+    n = int(x.shape[0])
+    dev = x.device.index or 0
+    sh = _shape(d_in, width, n_sine)
+    if value is None:
+        value = torch.empty(n, dtype=torch.float32, device=x.device)
+    if grad is None:
+        grad = torch.empty((n, 3), dtype=torch.float32, device=x.device)
+    _check(load_library().siren_forward_tangent(
+        _byref(sh), _dev_ptr(params, torch.float32, tuple(params.shape), "params", dev, False), n,
+        _dev_ptr(x, torch.float32, (n, d_in), "x", dev, False), _dev_ptr(value, torch.float32, (n,), "value", dev),
+        _dev_ptr(grad, torch.float32, (n, 3), "grad", dev), _stream_ptr(stream, dev)))
+    return value, grad
+
+
+def siren_backward(d_in, width, n_sine, params, x, dvalue, dgrad, dparams=None, dx=None, workspace=None,
+                   stream=None):
+    """dL/dparams (and dL/dx) from upstream dL/dN and dL/dgrad N (device tensors)."""
+    import torch
+    n = int(x.shape[0])
+    dev = x.device.index or 0
+    sh = _shape(d_in, width, n_sine)
+    if dparams is None:
+        dparams = torch.empty_like(params)
+    need = siren_workspace_bytes(d_in, width, n_sine, n)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    _check(load_library().siren_backward(
+        _byref(sh), _dev_ptr(params, torch.float32, tuple(params.shape), "params", dev, False), n,
+        _dev_ptr(x, torch.float32, (n, d_in), "x", dev, n > 0),
+        _dev_ptr(dvalue, torch.float32, (n,), "dvalue", dev), _dev_ptr(dgrad, torch.float32, (n, 3), "dgrad", dev),
+        _dev_ptr(dparams, torch.float32, tuple(params.shape), "dparams", dev, False),
+        _dev_ptr(dx, torch.float32, (n, d_in), "dx", dev), c_void_p(workspace.data_ptr()), int(workspace.numel()),
+        _stream_ptr(stream, dev)))
+    return dparams, dx
+
+
+class Fit:
+    """Fitting state on one device: parameters, Adam moments, step counter."""
+
+    def __init__(self, d_in, width, n_sine, params: np.ndarray, device: int = 0, max_points: int = 1 << 19):
+        self.shape = (int(d_in), int(width), int(n_sine))
+        self.device = int(device)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        sh = _shape(*self.shape)
+        h = c_void_p()
+        _check(load_library().fit_create(_byref(sh), p.ctypes.data_as(c_void_p), self.device, int(max_points),
+                                         _byref(h)))
+        self._h = h
+        self.n_params = p.size
+
+    def params(self) -> np.ndarray:
+        """Copy of the parameters (synchronises the device)."""
+        out = np.empty(self.n_params, np.float32)
+        _check(load_library().fit_read_state(self._h, out.ctypes.data_as(c_void_p), None, None))
+        return out
+
+    def state(self):
+        """(params, m, v, step) as numpy arrays (synchronises): a checkpoint."""
+        arrs = [np.empty(self.n_params, np.float32) for _ in range(3)]
+        _check(load_library().fit_read_state(self._h, *[a.ctypes.data_as(c_void_p) for a in arrs]))
+        return arrs[0], arrs[1], arrs[2], self.step
+
+    def load_state(self, params, m, v, step):
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (params, m, v)]
+        for a in arrs:
+            if a.size != self.n_params:
+                raise NnmError(-1, f"state arrays need {self.n_params} entries")
+        _check(load_library().fit_write_state(self._h, *[a.ctypes.data_as(c_void_p) for a in arrs]))
+        _check(load_library().fit_set_step(self._h, int(step)))
+
+    @property
+    def step(self) -> int:
+        return int(load_library().fit_get_step(self._h))
+
+    def _batch(self, surf_x, surf_n, unif_x, unif_sdf):
+        import torch
+        dev = self.device
+        ns, nu = int(surf_x.shape[0]), int(unif_x.shape[0])
+        b = _FitBatch(ns, nu, _dev_ptr(surf_x, torch.float32, (ns, 3), "surf_x", dev, False),
+                      _dev_ptr(surf_n, torch.float32, (ns, 3), "surf_n", dev, False),
+                      _dev_ptr(unif_x, torch.float32, (nu, 3), "unif_x", dev, False),
+                      _dev_ptr(unif_sdf, torch.float32, (nu,), "unif_sdf", dev, False))
+        return b
+
+    def step_adam(self, surf_x, surf_n, unif_x, unif_sdf, lr=1e-4, beta1=0.9, beta2=0.999, eps=1e-8, loss4=None,
+                  stream=None):
+        """One fitting step (fit_step); loss4: optional device [4] tensor."""
+        import torch
+        b = self._batch(surf_x, surf_n, unif_x, unif_sdf)
+        opt = _Adam(lr, beta1, beta2, eps)
+        lp = _dev_ptr(loss4, torch.float32, (4,), "loss4", self.device)
+        _check(load_library().fit_step(self._h, _byref(b), _byref(opt), lp, _stream_ptr(stream, self.device)))
+
+    def loss_grad(self, surf_x, surf_n, unif_x, unif_sdf, loss4, dparams, stream=None):
+        import torch
+        b = self._batch(surf_x, surf_n, unif_x, unif_sdf)
+        _check(load_library().fit_loss_grad(
+            self._h, _byref(b), _dev_ptr(loss4, torch.float32, (4,), "loss4", self.device),
+            _dev_ptr(dparams, torch.float32, (self.n_params,), "dparams", self.device, False),
+            _stream_ptr(stream, self.device)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().fit_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,2 +1,405 @@
-// fit_kernels.hip -- placeholder until the fitting kernels land.
+// fit_kernels.hip -- fitting a SIREN through its analytic gradient (double
+// backward) on gfx950, in float32.
+//
+// One fused kernel per batch of points, tile by tile (8 points x the four
+// columns [h | G_x G_y G_z] per wave, the tangent mode of the evaluator):
+//   forward   layer by layer with the shared-forward tangent (Alg. 2 in the
+//             G_i form), writing each layer's pre-activations (revolutions)
+//             and inputs to a workspace laid out [neuron][column];
+//   adjoints  of the loss terms, or the caller's upstream adjoints;
+//   reverse   through primal and tangent:
+//               abar_i  = cos(a_i) hbar_{i+1} - sin(a_i) sum_j Tbar_{i+1,j} dA_{i,j}
+//               dAbar_i = cos(a_i) Tbar_{i+1}
+//               [hbar_i | Tbar_i] = W_i^T [abar_i | dAbar_i]   (32x32x2 MFMAs)
+//             overwriting the pre-activations with [abar_i | dAbar_i].
+// The parameter gradient is then W_i-bar = sum over columns [abar|dAbar] X^T:
+// plain GEMMs / GEMVs over the workspace, issued by the host.
 #include "nnm_kernels.h"
+#include "siren_tile.h"
+
+namespace nnm {
+
+constexpr float kTwoPiF = 6.28318530717958647692f;
+
+// Sum over the four lanes of each quad.
+__device__ inline float quad_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));  // [1,0,3,2]
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
+  return v;
+}
+
+// ------------------------------------------------------------ packing (fp32)
+// Flat parameters (row major [out][in] per layer) -> the layouts the tile uses.
+__global__ void k_fit_pack(FitPackArgs A) {
+  const int H = A.width, K = A.n_sine, MB = H / 32, d_in = A.d_in;
+  const long long n_a0 = 3LL * MB * 64;
+  const long long n_bh = (long long)(K - 1) * H;
+  const long long n_wk = H;
+  const long long n_ah = (long long)(K - 1) * H * H;  // per copy (forward, transposed)
+  const long long total = n_a0 + n_bh + n_wk + 2 * n_ah + H + 1;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    long long i = e;
+    if (i < n_a0) {
+      const int lane = (int)(i % 64), mb = (int)((i / 64) % MB), ks = (int)(i / (64 * MB));
+      const int row = 32 * mb + lane % 32, k = 2 * ks + lane / 32;
+      float v = 0.f;
+      if (k < d_in)
+        v = A.params[A.w_off[0] + (long long)row * d_in + k];
+      else if (k == d_in)
+        v = A.params[A.b_off[0] + row];
+      A.a0[i] = v / kTwoPiF;
+      continue;
+    }
+    i -= n_a0;
+    if (i < n_bh) {
+      const int layer = 1 + (int)(i / H), slot = (int)(i % H);
+      const int mb = slot / 32, g = (slot / 16) % 2, r = slot % 16;
+      A.bh[i] = A.params[A.b_off[layer] + acc_row(mb, g, r)] / kTwoPiF;
+      continue;
+    }
+    i -= n_bh;
+    if (i < n_wk) {
+      const int slot = (int)i, mb = slot / 32, g = (slot / 16) % 2, r = slot % 16;
+      A.wk[i] = A.params[A.w_off[K] + acc_row(mb, g, r)];
+      continue;
+    }
+    i -= n_wk;
+    if (i < 2 * n_ah) {
+      const bool transposed = i >= n_ah;
+      const long long j = transposed ? i - n_ah : i;
+      const int layer = 1 + (int)(j / ((long long)H * H));
+      const long long w = j % ((long long)H * H);
+      // f32x4 group (q, mb, lane), element e
+      const int e4 = (int)(w % 4), lane = (int)((w / 4) % 64), mb = (int)((w / 256) % MB), q = (int)(w / (256 * MB));
+      const int ks = 4 * q + e4, row = 32 * mb + lane % 32, kn = kperm_2(ks, lane / 32);
+      const long long base = A.w_off[layer];
+      if (!transposed)
+        A.ah[j] = A.params[base + (long long)row * H + kn] / kTwoPiF;
+      else
+        A.aht[j] = A.params[base + (long long)kn * H + row];  // W^T[row = input][k = output]
+      continue;
+    }
+    i -= 2 * n_ah;
+    if (i < H) {
+      const int slot = (int)i, mb = slot / 32, g = (slot / 16) % 2, r = slot % 16, row = acc_row(mb, g, r);
+      const long long b = A.w_off[0] + (long long)row * d_in;
+      A.w0t[i] = make_float4(A.params[b], A.params[b + 1], A.params[b + 2], d_in == 4 ? A.params[b + 3] : 0.f);
+      continue;
+    }
+    A.bk[0] = A.params[A.b_off[K]];
+  }
+}
+
+// --------------------------------------------------------- fused fwd + bwd
+template <int H>
+__global__ void __launch_bounds__(kBlockThreads) k_fit_fb(FitArgs A) {
+  constexpr int MB = H / 32;
+  __shared__ NetSmem<H> sm;
+  __shared__ float4 s_w0t[H];
+  stage_net<H>(&sm, A.L);
+  for (int i = threadIdx.x; i < H; i += blockDim.x) s_w0t[i] = A.w0t[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 31;
+  const int g = lane >> 5;
+  const int q = col >> 2, c = col & 3;
+  const int waves = kBlockThreads / 64;
+  const int wave = blockIdx.x * waves + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * waves;
+  const int ntiles = (A.n + 7) / 8;
+  const long long Kc = A.Kc;
+  const int K = A.L.n_sine;
+  SirenTile<H, PREC_FP32, true> tile;
+  float lsum[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int t = wave; t < ntiles; t += nwaves) {
+    const int p = t * 8 + q;
+    const bool live = p < A.n;
+    const long long gcol = (long long)t * 32 + col;
+    // ---- inputs
+    const float* xp = nullptr;
+    bool surf = false;
+    if (live) {
+      if (A.mode == 0) {
+        surf = p < A.n_surf;
+        xp = surf ? A.x0 + 3LL * p : A.x1 + 3LL * (p - A.n_surf);
+      } else {
+        xp = A.x0 + (long long)A.L.d_in * p;
+      }
+    }
+    float4 in = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (xp) {
+      in.x = xp[0];
+      in.y = xp[1];
+      in.z = xp[2];
+      if (A.L.d_in == 4) in.w = xp[3];
+    }
+    // ---- forward: store pre-activations (revolutions) and layer inputs
+    f32x16_t acc[MB];
+    NNM_MEM_FENCE();
+    tile.layer0_acc(A.L, in, c, acc);
+    for (int layer = 0; layer < K; ++layer) {
+      if (layer > 0) tile.hidden_acc(&sm, A.L, layer, c, acc);
+      // [column][neuron] slabs: rows 32 mb + 8 b + 4 g .. +3 are 16 contiguous bytes
+      float4* pa = (float4*)(A.ws_abar + ((long long)layer * Kc + gcol) * H + 4 * g);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          pa[(32 * mb + 8 * b) / 4] = make_float4(acc[mb][4 * b], acc[mb][4 * b + 1], acc[mb][4 * b + 2], acc[mb][4 * b + 3]);
+      tile.activate(acc, c, layer == 0 || A.L.reduce_hidden != 0);
+      float4* px = (float4*)(A.ws_x + ((long long)layer * Kc + gcol) * H + 4 * g);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          px[(32 * mb + 8 * b) / 4] = make_float4(tile.act[mb][4 * b], tile.act[mb][4 * b + 1], tile.act[mb][4 * b + 2],
+                                                  tile.act[mb][4 * b + 3]);
+    }
+    const float val = tile.output(&sm, A.L, c);
+    const float N = quad_bcast<0>(val), gx = quad_bcast<1>(val), gy = quad_bcast<2>(val),
+                gz = quad_bcast<3>(val);
+    // ---- adjoints dL/dN, dL/dgrad N of this point
+    float Nbar = 0.f, gb[3] = {0.f, 0.f, 0.f};
+    if (live) {
+      if (A.mode == 0) {
+        if (surf) {
+          const float* np_ = A.surf_n + 3LL * p;
+          const float nx = np_[0], ny = np_[1], nz = np_[2];
+          Nbar = (N > 0.f ? 1.f : (N < 0.f ? -1.f : 0.f)) * A.inv_ns;
+          gb[0] = -nx * A.inv_ns;
+          gb[1] = -ny * A.inv_ns;
+          gb[2] = -nz * A.inv_ns;
+          if (c == 0 && g == 0) {
+            lsum[0] += fabsf(N);
+            lsum[1] += 1.f - (nx * gx + ny * gy + nz * gz);
+          }
+        } else {
+          const float sdf = A.unif_sdf[p - A.n_surf];
+          const float dlt = N - sdf;
+          Nbar = (dlt > 0.f ? 1.f : (dlt < 0.f ? -1.f : 0.f)) * A.inv_nu;
+          const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
+          const float s = gn > 0.f ? 2.f * (gn - 1.f) / gn * A.inv_nu : 0.f;
+          gb[0] = s * gx;
+          gb[1] = s * gy;
+          gb[2] = s * gz;
+          if (c == 0 && g == 0) {
+            lsum[2] += fabsf(dlt);
+            lsum[3] += (gn - 1.f) * (gn - 1.f);
+          }
+        }
+      } else {
+        Nbar = A.dvalue ? A.dvalue[p] : 0.f;
+        if (A.dgrad) {
+          gb[0] = A.dgrad[3LL * p];
+          gb[1] = A.dgrad[3LL * p + 1];
+          gb[2] = A.dgrad[3LL * p + 2];
+        }
+      }
+    }
+    const float adjc = (c == 0) ? Nbar : (c == 1 ? gb[0] : (c == 2 ? gb[1] : gb[2]));
+    if (g == 0) A.adj[gcol] = adjc;
+    // ---- reverse: X-bar of the output layer, then layer by layer
+    NNM_MEM_FENCE();
+    float xbar[MB][16];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) xbar[mb][r] = sm.wk[acc_slot(mb, g, r)] * adjc;
+    for (int layer = K - 1; layer >= 0; --layer) {
+      float4* pa = (float4*)(A.ws_abar + ((long long)layer * Kc + gcol) * H + 4 * g);
+      const bool reduce = layer == 0 || A.L.reduce_hidden;
+      NNM_MEM_FENCE();
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const float4 v4 = pa[(32 * mb + 8 * b) / 4];  // primal: a / 2pi; tangent: dA / 2pi
+          const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
+          float ab4[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = 4 * b + i;
+            const float v = vv[i];
+            float rp = quad_bcast<0>(v);
+            if (reduce) rp = fract_rev(rp);
+            const float cs = cos_rev(rp), sn = sin_rev(rp);
+            const float xb = xbar[mb][r];
+            const float prod = (c == 0) ? 0.f : xb * (kTwoPiF * v);  // Tbar_j dA_j
+            const float ssum = quad_sum(prod);
+            const float ab = (c == 0) ? fmaf(cs, xb, -sn * ssum) : cs * xb;
+            ab4[i] = ab;
+            xbar[mb][r] = ab;  // now [abar | dAbar] of this layer
+          }
+          pa[(32 * mb + 8 * b) / 4] = make_float4(ab4[0], ab4[1], ab4[2], ab4[3]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (layer > 0) {
+        f32x16_t nb[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) nb[mb][r] = 0.f;
+        const f32x4_t* AT = (const f32x4_t*)((const char*)A.aht + (long long)(layer - 1) * H * H * 4);
+        gemm_fp32<H>(xbar, AT, nb);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) xbar[mb][r] = nb[mb][r];
+      } else if (A.dx) {
+        // dL/dx through N: W_0^T abar_0 (primal column; the tangent seeds are constant)
+        float d4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const float4 w = s_w0t[acc_slot(mb, g, r)];
+            const float ab = xbar[mb][r];
+            d4[0] = fmaf(w.x, ab, d4[0]);
+            d4[1] = fmaf(w.y, ab, d4[1]);
+            d4[2] = fmaf(w.z, ab, d4[2]);
+            d4[3] = fmaf(w.w, ab, d4[3]);
+          }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) d4[j] += __shfl_xor(d4[j], 32);
+        if (c == 0 && g == 0 && live)
+          for (int j = 0; j < A.L.d_in; ++j) A.dx[(long long)A.L.d_in * p + j] = d4[j];
+      }
+    }
+  }
+  // per-wave loss partial sums (deterministic: fixed tile to wave map)
+  if (A.loss_part) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float v = lsum[j];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) A.loss_part[4LL * wave + j] = v;
+    }
+  }
+}
+
+// Column weights for the layer-0 gradient: w_j[col] = x_j (primal column), 1 on
+// the tangent column of coordinate j, else 0; plus the primal mask.
+__global__ void k_fit_vectors(FitVecArgs A) {
+  const long long Kc = A.Kc;
+  for (long long col = blockIdx.x * (long long)blockDim.x + threadIdx.x; col < Kc;
+       col += (long long)gridDim.x * blockDim.x) {
+    const long long p = col / 4;
+    const int c = (int)(col % 4);
+    float x[4] = {0.f, 0.f, 0.f, 0.f};
+    if (p < A.n) {
+      const float* xp;
+      if (A.mode == 0)
+        xp = p < A.n_surf ? A.x0 + 3 * p : A.x1 + 3 * (p - A.n_surf);
+      else
+        xp = A.x0 + (long long)A.d_in * p;
+      for (int j = 0; j < A.d_in; ++j) x[j] = xp[j];
+    }
+    const bool live = p < A.n;
+    A.mask[col] = (c == 0 && live) ? 1.f : 0.f;
+    for (int j = 0; j < A.d_in; ++j) {
+      float w = 0.f;
+      if (live) {
+        if (c == 0)
+          w = x[j];
+        else if (j < 3 && c == j + 1)
+          w = 1.f;
+      }
+      A.wvec[(long long)j * Kc + col] = w;
+    }
+  }
+}
+
+// Sums the per-wave loss partials in a fixed order (one block).
+__global__ void k_fit_loss_reduce(const float* part, int nwaves, float inv_ns, float inv_nu, float* loss4) {
+  __shared__ float sh[4][256];
+  const int t = threadIdx.x;
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int w = t; w < nwaves; w += blockDim.x)
+    for (int j = 0; j < 4; ++j) s[j] += part[4LL * w + j];
+  for (int j = 0; j < 4; ++j) sh[j][t] = s[j];
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (t < off)
+      for (int j = 0; j < 4; ++j) sh[j][t] += sh[j][t + off];
+    __syncthreads();
+  }
+  if (t == 0) {
+    loss4[0] = sh[0][0] * inv_ns;
+    loss4[1] = sh[1][0] * inv_ns;
+    loss4[2] = sh[2][0] * inv_nu;
+    loss4[3] = sh[3][0] * inv_nu;
+  }
+}
+
+// Adam (Kingma & Ba): m, v moments; bias corrections bc1 = 1 - beta1^t,
+// bc2 = 1 - beta2^t computed by the host in float64.
+__global__ void k_adam(float* params, const float* grad, float* m, float* v, long long n, float lr, float b1,
+                       float b2, float eps, float bc1, float bc2) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float gi = grad[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / bc1, vh = vi / bc2;
+    params[i] -= lr * mh / (sqrtf(vh) + eps);
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_fit_pack(const FitPackArgs& a, hipStream_t s) {
+  const long long H = a.width, K = a.n_sine;
+  const long long total = 3 * (H / 32) * 64 + (K - 1) * H + H + 2 * (K - 1) * H * H + H + 1;
+  const int grid = (int)std::min<long long>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fit_pack, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_fb(const FitArgs& a, int grid, hipStream_t s) {
+  switch (a.L.width) {
+    case 32: hipLaunchKernelGGL(k_fit_fb<32>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
+    case 64: hipLaunchKernelGGL(k_fit_fb<64>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
+    case 128: hipLaunchKernelGGL(k_fit_fb<128>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
+    case 256: hipLaunchKernelGGL(k_fit_fb<256>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_vectors(const FitVecArgs& a, hipStream_t s) {
+  const int grid = (int)std::min<long long>((a.Kc + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_fit_vectors, dim3(std::max(grid, 1)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_loss_reduce(const float* part, int nwaves, float inv_ns, float inv_nu, float* loss4,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_fit_loss_reduce, dim3(1), dim3(256), 0, s, part, nwaves, inv_ns, inv_nu, loss4);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* params, const float* grad, float* m, float* v, long long n, float lr, float b1,
+                       float b2, float eps, float bc1, float bc2, hipStream_t s) {
+  const int grid = (int)std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_adam, dim3(std::max(grid, 1)), dim3(256), 0, s, params, grad, m, v, n, lr, b1, b2, eps, bc1,
+                     bc2);
+  return hipGetLastError();
+}
+
+int fit_fb_grid(int width, int device) {
+  const void* fn = width == 32 ? (const void*)k_fit_fb<32>
+                   : width == 64 ? (const void*)k_fit_fb<64>
+                   : width == 128 ? (const void*)k_fit_fb<128>
+                                  : (const void*)k_fit_fb<256>;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlockThreads, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
+  return per_cu * cus;
+}
+
+}  // namespace nnm

@@ -2,8 +2,11 @@
 // Lipschitz bounds, weight packing for the gfx950 kernels, and the launch
 // sequence of multiscale sphere tracing.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <climits>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -554,6 +557,7 @@ static int points_common(const nnm_stack* s, int level, int64_t n, const float* 
   a.grad = grad;
   a.n = (int)n;
   a.raw = raw;
+  a.x_stride = 3;
   const long long want = ((long long)n + 31) / 32;
   const int grid = (int)std::max(1LL, std::min(want, (long long)lv.resident[2]));
   const hipError_t e = launch_points(lv.width, s->precision, a, grid, (hipStream_t)stream);
@@ -665,6 +669,446 @@ int nnm_read_net_file(const char* path, int32_t* d_in, int32_t* width, int32_t* 
   *n_sine = ns;
   *params_out = buf;
   *n_params = np;
+  return NNM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ fitting
+
+namespace {
+
+bool shape_ok(const nnm_net_shape* sh) {
+  return sh && (sh->d_in == 3 || sh->d_in == 4) && width_supported(sh->width) && sh->n_sine >= 1 &&
+         sh->n_sine <= kMaxSine;
+}
+
+// Layout of the fitting workspace for n points.
+struct FitLayout {
+  long long Kc = 0;
+  int nwaves = 0;
+  size_t off_a0, off_bh, off_wk, off_bk, off_ah, off_aht, off_w0t;
+  size_t off_abar, off_x, off_adj, off_mask, off_wvec, off_loss;
+  size_t total;
+};
+
+FitLayout fit_layout(const nnm_net_shape& sh, int64_t n, int grid) {
+  FitLayout L;
+  const size_t H = sh.width, K = sh.n_sine, MB = H / 32;
+  L.Kc = 32LL * ((n + 7) / 8);
+  if (L.Kc == 0) L.Kc = 32;
+  L.nwaves = grid * (kBlockThreads / 64);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  L.off_a0 = take(3 * MB * 64 * 4);
+  L.off_bh = take(std::max<size_t>(K - 1, 1) * H * 4);
+  L.off_wk = take(H * 4);
+  L.off_bk = take(4);
+  L.off_ah = take(std::max<size_t>(K - 1, 1) * H * H * 4);
+  L.off_aht = take(std::max<size_t>(K - 1, 1) * H * H * 4);
+  L.off_w0t = take(H * 16);
+  L.off_abar = take(K * H * (size_t)L.Kc * 4);
+  L.off_x = take(K * H * (size_t)L.Kc * 4);
+  L.off_adj = take((size_t)L.Kc * 4);
+  L.off_mask = take((size_t)L.Kc * 4);
+  L.off_wvec = take((size_t)sh.d_in * L.Kc * 4);
+  L.off_loss = take((size_t)L.nwaves * 16 + 16);
+  L.total = o;
+  return L;
+}
+
+std::mutex g_blas_mu;
+std::map<int, rocblas_handle> g_blas;  // one handle per device for the stateless entry points
+
+rocblas_handle blas_for_device(int device) {
+  std::lock_guard<std::mutex> lk(g_blas_mu);
+  auto it = g_blas.find(device);
+  if (it != g_blas.end()) return it->second;
+  rocblas_handle h = nullptr;
+  if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
+  rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed);
+  g_blas[device] = h;
+  return h;
+}
+
+int blas_fail(rocblas_status st, const char* what) {
+  return fail(NNM_E_DEVICE, "%s: rocBLAS status %d", what, (int)st);
+}
+
+// Packs `params` and runs the fused forward/adjoint/reverse kernel plus the
+// gradient products.  mode 0: loss (batch), mode 1: upstream adjoints.
+int fit_backward_impl(const nnm_net_shape& sh, const float* params, int device, int grid, char* ws,
+                      const FitLayout& FL, int mode, int64_t n, int64_t n_surf, const float* x0, const float* x1,
+                      const float* surf_n, const float* unif_sdf, const float* dvalue, const float* dgrad,
+                      float* loss4, float* dparams, float* dx, rocblas_handle blas, hipStream_t st) {
+  const int H = sh.width, K = sh.n_sine;
+  FitPackArgs pk{};
+  pk.params = params;
+  pk.d_in = sh.d_in;
+  pk.width = H;
+  pk.n_sine = K;
+  for (int i = 0; i <= K; ++i) {
+    int64_t wo, bo;
+    layer_offsets(sh.d_in, H, K, i, &wo, &bo);
+    pk.w_off[i] = wo;
+    pk.b_off[i] = bo;
+  }
+  pk.a0 = (float*)(ws + FL.off_a0);
+  pk.bh = (float*)(ws + FL.off_bh);
+  pk.wk = (float*)(ws + FL.off_wk);
+  pk.bk = (float*)(ws + FL.off_bk);
+  pk.ah = (float*)(ws + FL.off_ah);
+  pk.aht = (float*)(ws + FL.off_aht);
+  pk.w0t = (float4*)(ws + FL.off_w0t);
+  hipError_t e;
+  if ((e = launch_fit_pack(pk, st)) != hipSuccess) return hip_fail(e, "fit pack");
+  FitVecArgs va{};
+  va.Kc = FL.Kc;
+  va.n = (int)n;
+  va.n_surf = (int)n_surf;
+  va.mode = mode;
+  va.d_in = sh.d_in;
+  va.x0 = x0;
+  va.x1 = x1;
+  va.mask = (float*)(ws + FL.off_mask);
+  va.wvec = (float*)(ws + FL.off_wvec);
+  if ((e = launch_fit_vectors(va, st)) != hipSuccess) return hip_fail(e, "fit vectors");
+  FitArgs a{};
+  DevLevel& D = a.L;
+  D.a0 = pk.a0;
+  D.bh = pk.bh;
+  D.wk = pk.wk;
+  D.ah = pk.ah;
+  D.ah_stride = (long long)H * H * 4;
+  D.bk = 0.f;
+  D.bk_dev = pk.bk;
+  D.amplitude = 1.f;
+  D.d_in = sh.d_in;
+  D.width = H;
+  D.n_sine = K;
+  D.reduce_hidden = 1;
+  a.aht = pk.aht;
+  a.w0t = pk.w0t;
+  a.n = (int)n;
+  a.n_surf = (int)n_surf;
+  a.mode = mode;
+  a.x0 = x0;
+  a.x1 = x1;
+  a.surf_n = surf_n;
+  a.unif_sdf = unif_sdf;
+  a.dvalue = dvalue;
+  a.dgrad = dgrad;
+  a.inv_ns = n_surf > 0 ? 1.f / (float)n_surf : 0.f;
+  a.inv_nu = (n - n_surf) > 0 ? 1.f / (float)(n - n_surf) : 0.f;
+  a.ws_abar = (float*)(ws + FL.off_abar);
+  a.ws_x = (float*)(ws + FL.off_x);
+  a.adj = (float*)(ws + FL.off_adj);
+  a.loss_part = (float*)(ws + FL.off_loss);
+  a.dx = dx;
+  a.Kc = FL.Kc;
+  if ((e = launch_fit_fb(a, grid, st)) != hipSuccess) return hip_fail(e, "fit forward/backward");
+  if (loss4 && mode == 0)
+    if ((e = launch_fit_loss_reduce(a.loss_part, FL.nwaves, a.inv_ns, a.inv_nu, loss4, st)) != hipSuccess)
+      return hip_fail(e, "loss reduce");
+  // Gradient products over the workspace: each slab is [column][neuron], i.e.
+  // a column-major H x Kc matrix with leading dimension H.
+  std::lock_guard<std::mutex> lk(g_blas_mu);
+  rocblas_status bs;
+  if ((bs = rocblas_set_stream(blas, st)) != rocblas_status_success) return blas_fail(bs, "set stream");
+  rocblas_set_pointer_mode(blas, rocblas_pointer_mode_host);
+  const float one = 1.f, zero = 0.f;
+  const int Kc = (int)FL.Kc;
+  const float* abar = a.ws_abar;
+  const float* X = a.ws_x;
+  const size_t LS = (size_t)H * FL.Kc;  // floats per layer slab
+  for (int i = 1; i < K; ++i) {
+    // W_i-bar[out][in] = sum_col abar_i[col][out] X_i[col][in], X_i = inputs of layer i;
+    // column-major C (in x out) = X (H x Kc) * abar^T (Kc x H).
+    bs = rocblas_sgemm(blas, rocblas_operation_none, rocblas_operation_transpose, H, H, Kc, &one, X + (i - 1) * LS, H,
+                       abar + i * LS, H, &zero, dparams + pk.w_off[i], H);
+    if (bs != rocblas_status_success) return blas_fail(bs, "hidden weight gradient");
+  }
+  for (int i = 0; i < K; ++i) {
+    bs = rocblas_sgemv(blas, rocblas_operation_none, H, Kc, &one, abar + i * LS, H, va.mask, 1, &zero,
+                       dparams + pk.b_off[i], 1);
+    if (bs != rocblas_status_success) return blas_fail(bs, "bias gradient");
+  }
+  // W_0-bar[out][j] = sum_col abar_0[col][out] w_j[col]; column-major C (d_in x out).
+  bs = rocblas_sgemm(blas, rocblas_operation_transpose, rocblas_operation_transpose, sh.d_in, H, Kc, &one, va.wvec,
+                     Kc, abar, H, &zero, dparams + pk.w_off[0], sh.d_in);
+  if (bs != rocblas_status_success) return blas_fail(bs, "first-layer gradient");
+  bs = rocblas_sgemv(blas, rocblas_operation_none, H, Kc, &one, X + (K - 1) * LS, H, a.adj, 1, &zero,
+                     dparams + pk.w_off[K], 1);
+  if (bs != rocblas_status_success) return blas_fail(bs, "output-layer gradient");
+  rocblas_set_pointer_mode(blas, rocblas_pointer_mode_device);
+  bs = rocblas_sdot(blas, Kc, a.adj, 1, va.mask, 1, dparams + pk.b_off[K]);
+  rocblas_set_pointer_mode(blas, rocblas_pointer_mode_host);
+  if (bs != rocblas_status_success) return blas_fail(bs, "output-bias gradient");
+  return NNM_OK;
+}
+
+int current_device(int* dev) {
+  return hipGetDevice(dev) == hipSuccess ? NNM_OK : fail(NNM_E_DEVICE, "hipGetDevice failed");
+}
+
+}  // namespace
+
+struct nnm_fit {
+  int device = 0;
+  nnm_net_shape shape{};
+  int64_t n_params = 0;
+  int64_t max_points = 0;
+  int grid = 1;
+  float* state = nullptr;  // params | m | v | grad
+  char* ws = nullptr;
+  FitLayout layout{};
+  rocblas_handle blas = nullptr;
+  int64_t step = 0;
+};
+
+extern "C" {
+
+int64_t siren_workspace_bytes(const nnm_net_shape* shape, int64_t n) {
+  if (!shape_ok(shape) || n < 0) return -1;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  return (int64_t)fit_layout(*shape, n, fit_fb_grid(shape->width, dev)).total;
+}
+
+int siren_forward_tangent(const nnm_net_shape* shape, const float* params, int64_t n, const float* x, float* value,
+                          float* grad, void* stream) {
+  g_err.clear();
+  if (!shape_ok(shape)) return fail(NNM_E_UNSUPPORTED, "unsupported network shape");
+  if (n < 0 || n > (int64_t)INT_MAX / 8) return fail(NNM_E_INVAL, "n = %lld", (long long)n);
+  if (n == 0) return NNM_OK;
+  if (!params || !x || (!value && !grad)) return fail(NNM_E_INVAL, "null argument");
+  int dev;
+  if (current_device(&dev) != NNM_OK) return NNM_E_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  // Pack into a small stream-ordered scratch, then evaluate with the points kernel.
+  const FitLayout FL = fit_layout(*shape, 0, 1);
+  const size_t pack_bytes = FL.off_abar;
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, pack_bytes, st);
+  if (e != hipSuccess) return fail(NNM_E_NOMEM, "hipMallocAsync(%zu)", pack_bytes);
+  char* w = (char*)ws;
+  FitPackArgs pk{};
+  pk.params = params;
+  pk.d_in = shape->d_in;
+  pk.width = shape->width;
+  pk.n_sine = shape->n_sine;
+  for (int i = 0; i <= shape->n_sine; ++i) {
+    int64_t wo, bo;
+    layer_offsets(shape->d_in, shape->width, shape->n_sine, i, &wo, &bo);
+    pk.w_off[i] = wo;
+    pk.b_off[i] = bo;
+  }
+  pk.a0 = (float*)(w + FL.off_a0);
+  pk.bh = (float*)(w + FL.off_bh);
+  pk.wk = (float*)(w + FL.off_wk);
+  pk.bk = (float*)(w + FL.off_bk);
+  pk.ah = (float*)(w + FL.off_ah);
+  pk.aht = (float*)(w + FL.off_aht);
+  pk.w0t = (float4*)(w + FL.off_w0t);
+  int rc = NNM_OK;
+  if ((e = launch_fit_pack(pk, st)) != hipSuccess) rc = hip_fail(e, "pack");
+  if (rc == NNM_OK) {
+    PointsArgs a{};
+    DevLevel& D = a.L;
+    D.a0 = pk.a0;
+    D.bh = pk.bh;
+    D.wk = pk.wk;
+    D.ah = pk.ah;
+    D.ah_stride = (long long)shape->width * shape->width * 4;
+    D.bk_dev = pk.bk;
+    D.amplitude = 1.f;
+    D.d_in = shape->d_in;
+    D.width = shape->width;
+    D.n_sine = shape->n_sine;
+    D.reduce_hidden = 1;
+    a.x = x;
+    a.t = nullptr;
+    a.value = value;
+    a.grad = grad;
+    a.n = (int)n;
+    a.raw = 1;
+    a.x_stride = shape->d_in;
+    const int grid = (int)std::max(1LL, std::min(((long long)n + 31) / 32,
+                                                 (long long)resident_blocks(shape->width, NNM_PREC_FP32, 2, dev)));
+    if ((e = launch_points(shape->width, NNM_PREC_FP32, a, grid, st)) != hipSuccess) rc = hip_fail(e, "forward");
+  }
+  if ((e = hipFreeAsync(ws, st)) != hipSuccess && rc == NNM_OK) rc = hip_fail(e, "hipFreeAsync");
+  return rc;
+}
+
+int siren_backward(const nnm_net_shape* shape, const float* params, int64_t n, const float* x, const float* dvalue,
+                   const float* dgrad, float* dparams, float* dx, void* workspace, int64_t workspace_bytes,
+                   void* stream) {
+  g_err.clear();
+  if (!shape_ok(shape)) return fail(NNM_E_UNSUPPORTED, "unsupported network shape");
+  if (n < 0 || n > (int64_t)INT_MAX / 8) return fail(NNM_E_INVAL, "n = %lld", (long long)n);
+  if (!params || !dparams || (n > 0 && !x)) return fail(NNM_E_INVAL, "null argument");
+  int dev;
+  if (current_device(&dev) != NNM_OK) return NNM_E_DEVICE;
+  const int grid = fit_fb_grid(shape->width, dev);
+  const FitLayout FL = fit_layout(*shape, n, grid);
+  if (!workspace || workspace_bytes < (int64_t)FL.total)
+    return fail(NNM_E_INVAL, "workspace of %lld bytes, %zu needed", (long long)workspace_bytes, FL.total);
+  rocblas_handle h = blas_for_device(dev);
+  if (!h) return fail(NNM_E_DEVICE, "rocblas handle");
+  return fit_backward_impl(*shape, params, dev, grid, (char*)workspace, FL, 1, n, 0, x, nullptr, nullptr, nullptr,
+                           dvalue, dgrad, nullptr, dparams, dx, h, (hipStream_t)stream);
+}
+
+int fit_create(const nnm_net_shape* shape, const float* params, int device, int64_t max_points, nnm_fit** out) {
+  g_err.clear();
+  if (!out) return fail(NNM_E_INVAL, "null output handle");
+  *out = nullptr;
+  if (!shape_ok(shape)) return fail(NNM_E_UNSUPPORTED, "unsupported network shape");
+  if (!params) return fail(NNM_E_INVAL, "null params");
+  if (max_points < 1 || max_points > (int64_t)INT_MAX / 8) return fail(NNM_E_INVAL, "max_points %lld", (long long)max_points);
+  const int64_t P = param_count(shape->d_in, shape->width, shape->n_sine);
+  for (int64_t k = 0; k < P; ++k)
+    if (!std::isfinite(params[k])) return fail(NNM_E_NONFINITE, "non-finite parameter %lld", (long long)k);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(NNM_E_INVAL, "device %d", device);
+  DeviceGuard guard(device);
+  nnm_fit* f = new nnm_fit();
+  f->device = device;
+  f->shape = *shape;
+  f->n_params = P;
+  f->max_points = max_points;
+  f->grid = fit_fb_grid(shape->width, device);
+  f->layout = fit_layout(*shape, max_points, f->grid);
+  hipError_t e;
+  if ((e = hipMalloc((void**)&f->state, (size_t)P * 4 * 4)) != hipSuccess ||
+      (e = hipMalloc((void**)&f->ws, f->layout.total)) != hipSuccess) {
+    fit_free(f);
+    return fail(NNM_E_NOMEM, "fit allocation (%zu bytes): %s", f->layout.total, hipGetErrorString(e));
+  }
+  if ((e = hipMemcpy(f->state, params, (size_t)P * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemset(f->state + P, 0, (size_t)P * 4 * 3)) != hipSuccess) {
+    fit_free(f);
+    return hip_fail(e, "fit upload");
+  }
+  if (rocblas_create_handle(&f->blas) != rocblas_status_success) {
+    fit_free(f);
+    return fail(NNM_E_DEVICE, "rocblas handle");
+  }
+  rocblas_set_atomics_mode(f->blas, rocblas_atomics_not_allowed);
+  *out = f;
+  return NNM_OK;
+}
+
+void fit_free(nnm_fit* f) {
+  if (!f) return;
+  DeviceGuard guard(f->device);
+  if (f->blas) rocblas_destroy_handle(f->blas);
+  if (f->state) (void)hipFree(f->state);
+  if (f->ws) (void)hipFree(f->ws);
+  delete f;
+}
+
+static int fit_check_batch(const nnm_fit* f, const nnm_fit_batch* b) {
+  if (!f || !b) return fail(NNM_E_INVAL, "null argument");
+  if (b->n_surf < 0 || b->n_unif < 0) return fail(NNM_E_INVAL, "negative batch size");
+  const int64_t n = b->n_surf + b->n_unif;
+  if (n > f->max_points) return fail(NNM_E_INVAL, "batch of %lld points exceeds max_points %lld", (long long)n,
+                                     (long long)f->max_points);
+  if (b->n_surf > 0 && (!b->surf_x || !b->surf_n)) return fail(NNM_E_INVAL, "null surface arrays");
+  if (b->n_unif > 0 && (!b->unif_x || !b->unif_sdf)) return fail(NNM_E_INVAL, "null uniform arrays");
+  if (f->shape.d_in != 3) return fail(NNM_E_UNSUPPORTED, "the fitting loss takes 3-D points");
+  return NNM_OK;
+}
+
+int fit_loss_grad(nnm_fit* f, const nnm_fit_batch* b, float* loss4, float* dparams, void* stream) {
+  g_err.clear();
+  int rc = fit_check_batch(f, b);
+  if (rc != NNM_OK) return rc;
+  if (!dparams) return fail(NNM_E_INVAL, "null dparams");
+  DeviceGuard guard(f->device);
+  const int64_t n = b->n_surf + b->n_unif;
+  const FitLayout FL = fit_layout(f->shape, n, f->grid);
+  return fit_backward_impl(f->shape, f->state, f->device, f->grid, f->ws, FL, 0, n, b->n_surf, b->surf_x, b->unif_x,
+                           b->surf_n, b->unif_sdf, nullptr, nullptr, loss4, dparams, nullptr, f->blas,
+                           (hipStream_t)stream);
+}
+
+int fit_step(nnm_fit* f, const nnm_fit_batch* b, const nnm_adam* opt, float* loss4, void* stream) {
+  g_err.clear();
+  if (!opt) return fail(NNM_E_INVAL, "null optimiser parameters");
+  if (!(opt->lr > 0.f) || !(opt->beta1 >= 0.f && opt->beta1 < 1.f) || !(opt->beta2 >= 0.f && opt->beta2 < 1.f) ||
+      !(opt->eps > 0.f))
+    return fail(NNM_E_INVAL, "bad Adam parameters");
+  int rc = fit_check_batch(f, b);
+  if (rc != NNM_OK) return rc;
+  DeviceGuard guard(f->device);
+  const int64_t P = f->n_params;
+  float* params = f->state;
+  float* m = f->state + P;
+  float* v = f->state + 2 * P;
+  float* grad = f->state + 3 * P;
+  const int64_t n = b->n_surf + b->n_unif;
+  const FitLayout FL = fit_layout(f->shape, n, f->grid);
+  hipStream_t st = (hipStream_t)stream;
+  rc = fit_backward_impl(f->shape, params, f->device, f->grid, f->ws, FL, 0, n, b->n_surf, b->surf_x, b->unif_x,
+                         b->surf_n, b->unif_sdf, nullptr, nullptr, loss4, grad, nullptr, f->blas, st);
+  if (rc != NNM_OK) return rc;
+  const int64_t t = f->step + 1;
+  const double bc1 = 1.0 - std::pow((double)opt->beta1, (double)t);
+  const double bc2 = 1.0 - std::pow((double)opt->beta2, (double)t);
+  const hipError_t e = launch_adam(params, grad, m, v, P, opt->lr, opt->beta1, opt->beta2, opt->eps, (float)bc1,
+                                   (float)bc2, st);
+  if (e != hipSuccess) return hip_fail(e, "adam");
+  f->step = t;
+  return NNM_OK;
+}
+
+int fit_state(nnm_fit* f, float** params, float** adam_m, float** adam_v, int64_t* n_params) {
+  if (!f) return fail(NNM_E_INVAL, "null fit");
+  if (params) *params = f->state;
+  if (adam_m) *adam_m = f->state + f->n_params;
+  if (adam_v) *adam_v = f->state + 2 * f->n_params;
+  if (n_params) *n_params = f->n_params;
+  return NNM_OK;
+}
+
+int fit_read_state(nnm_fit* f, float* params, float* adam_m, float* adam_v) {
+  if (!f) return fail(NNM_E_INVAL, "null fit");
+  DeviceGuard guard(f->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "synchronize");
+  const size_t bytes = (size_t)f->n_params * 4;
+  float* dst[3] = {params, adam_m, adam_v};
+  for (int i = 0; i < 3; ++i)
+    if (dst[i] && (e = hipMemcpy(dst[i], f->state + i * f->n_params, bytes, hipMemcpyDeviceToHost)) != hipSuccess)
+      return hip_fail(e, "read state");
+  return NNM_OK;
+}
+
+int fit_write_state(nnm_fit* f, const float* params, const float* adam_m, const float* adam_v) {
+  if (!f) return fail(NNM_E_INVAL, "null fit");
+  DeviceGuard guard(f->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "synchronize");
+  const size_t bytes = (size_t)f->n_params * 4;
+  const float* src[3] = {params, adam_m, adam_v};
+  for (int i = 0; i < 3; ++i)
+    if (src[i] && (e = hipMemcpy(f->state + i * f->n_params, src[i], bytes, hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "write state");
+  return NNM_OK;
+}
+
+int64_t fit_get_step(const nnm_fit* f) { return f ? f->step : -1; }
+
+int fit_set_step(nnm_fit* f, int64_t step) {
+  if (!f || step < 0) return fail(NNM_E_INVAL, "bad argument");
+  f->step = step;
   return NNM_OK;
 }
 

@@ -62,6 +62,7 @@ struct PointsArgs {
   float* grad;   // may be null
   int n;
   int raw;  // 1: the network N alone; 0: the scene function f
+  int x_stride;  // floats per point in x: 3, or 4 with the time in x[3]
 };
 
 // Device packing of flat float32 parameters for the fitting kernels.
@@ -94,8 +95,8 @@ struct FitArgs {
   const float* dvalue;  // upstream dL/dN [n] or null
   const float* dgrad;   // upstream dL/d grad N [n][3] or null
   float inv_ns, inv_nu;
-  float* ws_abar;  // [K][H][Kc]: pre-activations, then [abar | dAbar]
-  float* ws_x;     // [K][H][Kc]: inputs of layers 1..K
+  float* ws_abar;  // [K][Kc][H]: pre-activations, then [abar | dAbar]
+  float* ws_x;     // [K][Kc][H]: inputs of layers 1..K
   float* adj;      // [Kc]: dL/dN or dL/d grad N per column
   float* loss_part;  // [waves][4] or null
   float* dx;         // [n][d_in] or null

@@ -271,10 +271,11 @@ __global__ void __launch_bounds__(kBlockThreads) k_points(PointsArgs A) {
     const bool live = i < A.n;
     float x = 0.f, y = 0.f, z = 0.f, tt = 0.f;
     if (live) {
-      x = A.x[3 * i + 0];
-      y = A.x[3 * i + 1];
-      z = A.x[3 * i + 2];
-      tt = A.t ? A.t[i] : 0.f;
+      const long long b = (long long)A.x_stride * i;
+      x = A.x[b + 0];
+      y = A.x[b + 1];
+      z = A.x[b + 2];
+      tt = A.x_stride == 4 ? A.x[b + 3] : (A.t ? A.t[i] : 0.f);
     }
     float cx, cy;
     center_at(A.B, tt, cx, cy);

@@ -1,0 +1,187 @@
+"""GPU parity of the fitting path (forward with tangent, double backward,
+Adam) against the float64 oracle, plus structural checks.
+
+Gates: value and gradient relative L2 <= 1e-5; parameter gradient relative
+L2 <= 1e-4 (float32 accumulation over thousands of points); Adam update within
+1e-3 lr of the oracle's update from the oracle gradient, except where the
+gradient is below 1e-6 of its largest entry.
+"""
+
+import numpy as np
+import pytest
+
+import nnm_inputs as ni
+import paper_2201_09147_amd as nnm
+from oracle import fitting as F
+from tests.parity import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    import torch
+    return torch.device("cuda", 0)
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(_dev())
+
+
+def _batch(ns, nu, step=0):
+    return ni.torus_batch(step, ns, nu)
+
+
+@pytest.mark.parametrize("seed,d_in,H,K", [(6, 3, 256, 3), (2, 3, 64, 2), (4, 4, 256, 3)])
+def test_forward_tangent(seed, d_in, H, K):
+    net = ni.siren_init(seed, d_in, H, K, 1.0, normalise=False)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, size=(3000 + 5, d_in)).astype(np.float32)
+    v, g = nnm.siren_forward_tangent(d_in, H, K, _t(net.flat()), _t(x))
+    rv, rg = F.net_value_grad(net.layers, x.astype(np.float64))
+    assert rel_l2(v.cpu().numpy(), rv) <= 1e-5
+    assert rel_l2(g.cpu().numpy(), rg) <= 1e-5
+
+
+@pytest.mark.parametrize("seed,d_in,H,K", [(6, 3, 256, 3), (2, 3, 64, 2), (4, 4, 256, 3)])
+def test_backward_upstream_adjoints(seed, d_in, H, K):
+    import torch
+    net = ni.siren_init(seed, d_in, H, K, 1.0, normalise=False)
+    rng = np.random.default_rng(4)
+    n = 2000 + 3
+    x = rng.uniform(-1, 1, size=(n, d_in)).astype(np.float32)
+    dv = rng.normal(size=n).astype(np.float32)
+    dg = rng.normal(size=(n, 3)).astype(np.float32)
+    dx = torch.empty((n, d_in), dtype=torch.float32, device=_dev())
+    dp, dx = nnm.siren_backward(d_in, H, K, _t(net.flat()), _t(x), _t(dv), _t(dg), dx=dx)
+    grads, rdx = F.backward(net.layers, x.astype(np.float64), dv.astype(np.float64), dg.astype(np.float64))
+    ref = F.flatten_grads(grads)
+    e = rel_l2(dp.cpu().numpy(), ref)
+    print(f"backward H={H} K={K} d_in={d_in}: rel L2 dparams {e:.2e}")
+    assert e <= 1e-4
+    assert rel_l2(dx.cpu().numpy(), rdx) <= 1e-4
+
+
+def _fit(net, max_points):
+    return nnm.Fit(net.d_in, net.width, net.n_sine, net.flat(), 0, max_points)
+
+
+@pytest.mark.parametrize("ns,nu", [(256, 1024), (4096 + 3, 16384 + 5)])
+def test_loss_and_gradient(ns, nu):
+    import torch
+    net = ni.siren_init(6, 3, 256, 3, 1.0, normalise=False)
+    sx, sn, ux, us = _batch(ns, nu)
+    fit = _fit(net, ns + nu)
+    loss = torch.empty(4, dtype=torch.float32, device=_dev())
+    dp = torch.empty(net.n_params, dtype=torch.float32, device=_dev())
+    fit.loss_grad(_t(sx), _t(sn), _t(ux), _t(us), loss, dp)
+    terms, grads = F.loss_and_grad(net.layers, sx, sn, ux, us)
+    np.testing.assert_allclose(loss.cpu().numpy(), terms, rtol=1e-5, atol=1e-7)
+    e = rel_l2(dp.cpu().numpy(), F.flatten_grads(grads))
+    print(f"loss+grad ns={ns} nu={nu}: rel L2 {e:.2e}")
+    assert e <= 1e-4
+    fit.close()
+
+
+def test_adam_step_and_determinism():
+    import torch
+    net = ni.siren_init(6, 3, 256, 3, 1.0, normalise=False)
+    sx, sn, ux, us = _batch(512, 2048, 1)
+    fit = _fit(net, 4096)
+    dp1 = torch.empty(net.n_params, dtype=torch.float32, device=_dev())
+    dp2 = torch.empty_like(dp1)
+    loss = torch.empty(4, dtype=torch.float32, device=_dev())
+    args = (_t(sx), _t(sn), _t(ux), _t(us))
+    fit.loss_grad(*args, loss, dp1)
+    fit.loss_grad(*args, loss, dp2)
+    assert torch.equal(dp1, dp2), "gradient is not bitwise reproducible"
+    lr = 1e-4
+    fit.step_adam(*args, lr=lr)
+    p_gpu = fit.params()
+    _, grads = F.loss_and_grad(net.layers, sx, sn, ux, us)
+    g = F.flatten_grads(grads)
+    p_ref, _, _ = F.adam_update(net.flat(), g, np.zeros_like(g), np.zeros_like(g), 1, lr)
+    diff = np.abs(p_gpu.astype(np.float64) - p_ref)
+    big = np.abs(g) > 1e-6 * np.abs(g).max()
+    assert diff[big].max() <= 1e-3 * lr + 1e-7 * np.abs(p_ref[big]).max()
+    assert diff.max() <= 2.0 * lr + 1e-6
+    assert fit.step == 1
+    fit.close()
+
+
+def test_checkpoint_resume_is_bitwise():
+    import torch
+    net = ni.siren_init(6, 3, 64, 2, 1.0, normalise=False)
+    batches = [tuple(_t(a) for a in _batch(256, 1024, s)) for s in range(4)]
+    a = _fit(net, 2048)
+    for b in batches:
+        a.step_adam(*b, lr=1e-3)
+    pa = a.params()
+    b_ = _fit(net, 2048)
+    for b in batches[:2]:
+        b_.step_adam(*b, lr=1e-3)
+    ckpt = b_.state()
+    c = _fit(ni.siren_init(9, 3, 64, 2, 1.0, normalise=False), 2048)
+    c.load_state(*ckpt)
+    for b in batches[2:]:
+        c.step_adam(*b, lr=1e-3)
+    assert c.step == 4
+    assert np.array_equal(pa, c.params())
+    for f in (a, b_, c):
+        f.close()
+    del torch
+
+
+def test_autograd_function_matches_torch_double_backward():
+    import torch
+    from paper_2201_09147_amd.autograd import siren
+    net = ni.siren_init(6, 3, 256, 3, 1.0, normalise=False)
+    sx, sn, ux, us = _batch(128, 512, 2)
+    x = np.concatenate([sx, ux])
+    ns = sx.shape[0]
+    params = _t(net.flat()).requires_grad_(True)
+    xt = _t(x).requires_grad_(True)
+    N, g = siren(xt, params, 3, 256, 3)
+    loss = (N[:ns].abs().mean() + (1 - (_t(sn) * g[:ns]).sum(1)).mean() + (N[ns:] - _t(us)).abs().mean()
+            + ((g[ns:].norm(dim=1) - 1) ** 2).mean())
+    dparams, dx = torch.autograd.grad(loss, [params, xt])
+    # float64 CPU reference with torch's own double backward
+    ps = []
+    for W, b in net.layers:
+        ps += [torch.tensor(np.asarray(W, np.float64), requires_grad=True),
+               torch.tensor(np.asarray(b, np.float64), requires_grad=True)]
+    xr = torch.tensor(x.astype(np.float64), requires_grad=True)
+    h = xr
+    for i in range(4):
+        h = torch.nn.functional.linear(h, ps[2 * i], ps[2 * i + 1])
+        if i < 3:
+            h = torch.sin(h)
+    Nr = h[:, 0]
+    (gr,) = torch.autograd.grad(Nr.sum(), xr, create_graph=True)
+    lr_ = (Nr[:ns].abs().mean() + (1 - (torch.tensor(sn, dtype=torch.float64) * gr[:ns]).sum(1)).mean()
+           + (Nr[ns:] - torch.tensor(us, dtype=torch.float64)).abs().mean() + ((gr[ns:].norm(dim=1) - 1) ** 2).mean())
+    refs = torch.autograd.grad(lr_, ps + [xr])
+    ref_p = np.concatenate([r.detach().numpy().reshape(-1) for r in refs[:-1]])
+    assert rel_l2(dparams.cpu().numpy(), ref_p) <= 1e-4
+    assert rel_l2(dx.cpu().numpy(), refs[-1].detach().numpy()) <= 1e-4
+
+
+def test_full_size_fit_steps_decrease_loss():
+    """The fitting workload's batch (2^16 surface + 2^18 uniform points): finite,
+    reproducible, and the loss goes down over a few steps."""
+    import torch
+    scene = ni.make_scene("fit_torus_256x2")
+    ns, nu = scene.extra["n_surf"], scene.extra["n_unif"]
+    net = scene.levels[0].net
+    fit = _fit(net, ns + nu)
+    loss = torch.empty(4, dtype=torch.float32, device=_dev())
+    hist = []
+    for step in range(12):
+        b = tuple(_t(a) for a in ni.torus_batch(step, ns, nu))
+        fit.step_adam(*b, lr=1e-4, loss4=loss)
+        hist.append(loss.cpu().numpy().copy())
+    hist = np.array(hist)
+    print("loss terms per step:", hist.sum(1))
+    assert np.all(np.isfinite(hist))
+    assert hist[-1].sum() < hist[0].sum()
+    fit.close()
