@@ -98,6 +98,38 @@ def run_form(scene, precision, o, v, t, steps, warmup):
     return res
 
 
+def run_fit(steps, warmup):
+    """Fitting workload: (256,2) SIREN, 2^16 surface + 2^18 uniform torus points
+    per step, FP32 double backward + Adam (fit_step).  Batches are generated
+    before the timed region and cycled."""
+    import torch
+    import nnm_inputs as ni
+    import paper_2201_09147_amd as nnm
+    scene = ni.make_scene("fit_torus_256x2")
+    ns, nu = scene.extra["n_surf"], scene.extra["n_unif"]
+    net = scene.levels[0].net
+    dev = torch.device("cuda", 0)
+    batches = [tuple(torch.from_numpy(a).to(dev) for a in ni.torus_batch(s, ns, nu)) for s in range(4)]
+    fit = nnm.Fit(net.d_in, net.width, net.n_sine, net.flat(), 0, ns + nu)
+    loss = torch.empty(4, dtype=torch.float32, device=dev)
+    for i in range(warmup):
+        fit.step_adam(*batches[i % 4], lr=scene.extra["lr"], loss4=loss)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        fit.step_adam(*batches[i % 4], lr=scene.extra["lr"], loss4=loss)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    flop_point = 3 * 4 * 2 * (net.n_sine - 1) * net.width ** 2  # fwd+tangent, W^T products, weight grads
+    tflops = (ns + nu) * flop_point / (ms * 1e-3) / 1e12
+    fit.close()
+    log(f"[fit] {steps} steps: {ms:.3f} ms/step, {tflops:.1f} TFLOP/s (hidden layers)")
+    return {"workload": "fit_torus_256x2", "points_per_step": ns + nu, "ms_per_step": round(ms, 4),
+            "steps_per_s": round(1e3 / ms, 3), "points_per_s": round((ns + nu) / (ms * 1e-3), 1),
+            "hidden_tflops": round(tflops, 3), "frac_fp32_mfma_peak": round(tflops / PEAK_TFLOPS["fp32"], 5),
+            "final_loss4": [round(float(v_), 6) for v_ in loss.cpu().numpy()]}
+
+
 def roofline(form):
     dom = max(form["kernels"], key=lambda k: k["avg_ms"])
     peak = PEAK_TFLOPS[form["precision"]]
@@ -115,9 +147,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="stack3_1080p")
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16"])
-    ap.add_argument("--forms", default="fp32,bf16")
+    ap.add_argument("--forms", default="fp32,bf16,fp16")
     ap.add_argument("--cpu-rows-every", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fit-steps", type=int, default=10, help="fitting steps to time (0: skip)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): rays are independent, so a "
@@ -138,10 +173,20 @@ def main():
     log(f"workload {args.workload}: {n} rays, levels "
         + " |> ".join(f"({l.net.width},{l.net.n_sine - 1})" for l in scene.levels))
 
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 256 MiB read + 256 MiB written")
+        del src, dst
+
     forms = [f for f in args.forms.split(",") if f]
     if args.precision not in forms:
         forms.append(args.precision)
     results = {f: run_form(scene, f, o, v, t, args.steps, args.warmup) for f in forms}
+
+    fit = run_fit(args.fit_steps, 2) if args.fit_steps > 0 else None
 
     cpu = None
     errors = {}
@@ -192,6 +237,7 @@ def main():
         "roofline": roofline(head),
         "cpu_baseline": cpu,
         "errors_vs_oracle": errors,
+        "fit": fit,
         "forms": {f: {"rays_per_s": round(r["rays_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                       "roofline": roofline(r), "hits": r["hits"], "evals_per_level": r["evals_per_level"],
                       "frame_mfma_frac": round(sum(k["hidden_flops"] for k in r["kernels"])

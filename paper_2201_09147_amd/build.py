@@ -18,7 +18,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnnm.so")
 
 ARCH = os.environ.get("NNM_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["nnm_api.cpp", "trace_kernels.hip", "fit_kernels.hip"]
+SOURCES = ["nnm_api.cpp", "trace_kernels.hip", "trace_ws.hip", "fit_kernels.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}"]
@@ -54,7 +54,7 @@ def build(verbose: bool = False, defines=(), out=LIB, build_dir=BUILD_DIR) -> st
     with cf.ThreadPoolExecutor(max_workers=min(len(sources), os.cpu_count() or 1)) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose, defines, build_dir), sources))
     tmp = out + ".tmp"
-    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp, "-lrocblas"]
+    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")

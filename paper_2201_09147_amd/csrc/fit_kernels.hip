@@ -13,7 +13,7 @@
 //               [hbar_i | Tbar_i] = W_i^T [abar_i | dAbar_i]   (32x32x2 MFMAs)
 //             overwriting the pre-activations with [abar_i | dAbar_i].
 // The parameter gradient is then W_i-bar = sum over columns [abar|dAbar] X^T:
-// plain GEMMs / GEMVs over the workspace, issued by the host.
+// reductions over the workspace (split-K MFMA GEMM and column reductions).
 #include "nnm_kernels.h"
 #include "siren_tile.h"
 
@@ -348,7 +348,145 @@ __global__ void k_adam(float* params, const float* grad, float* m, float* v, lon
   }
 }
 
+// ------------------------------------------- weight-gradient reductions
+// Column reduction over a [Kc][H] slab: part[chunk][r][row] =
+// sum_{col in chunk} M[col][row] w_r[col] for R column-weight vectors (stride Kc).
+template <int R>
+__global__ void __launch_bounds__(256) k_colreduce(const float* __restrict__ M, int H, long long Kc,
+                                                   const float* __restrict__ w, int chunk, float* __restrict__ part) {
+  const int row = threadIdx.x;
+  if (row >= H) return;
+  const long long c0 = (long long)blockIdx.x * chunk;
+  const long long c1 = min(c0 + chunk, Kc);
+  float acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.f;
+  for (long long col = c0; col < c1; ++col) {
+    const float m = M[col * H + row];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = fmaf(m, w[r * Kc + col], acc[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) part[((long long)blockIdx.x * R + r) * H + row] = acc[r];
+}
+
+// dst_r[row * stride_r] = sum over chunks (fixed order) of part[chunk][r][row].
+__global__ void k_colreduce_final(const float* __restrict__ part, int nchunk, int R, int H, ColDst dst) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (row >= H) return;
+  float s = 0.f;
+  for (int c = 0; c < nchunk; ++c) s += part[((long long)c * R + r) * H + row];
+  dst.ptr[r][(long long)row * dst.stride[r]] = s;
+}
+
+// Weight gradient of a hidden layer, split over column chunks:
+// part[chunk][o][i] = sum_{col in chunk} abar[col][o] X[col][i] (32x32x2 fp32
+// MFMAs; wave w accumulates row blocks w, w+4, ... against every column block).
+template <int H>
+__global__ void __launch_bounds__(256) k_wgrad(const float* __restrict__ abar, const float* __restrict__ X,
+                                               long long Kc, int chunk, float* __restrict__ part) {
+  constexpr int MB = H / 32;
+  constexpr int RPW = MB >= 4 ? MB / 4 : 1;  // row blocks per wave
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 31, g = lane >> 5;
+  if (wave >= MB) return;  // small widths: fewer row blocks than waves
+  f32x16_t acc[RPW][MB];
+#pragma unroll
+  for (int a = 0; a < RPW; ++a)
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+  const long long c0 = (long long)blockIdx.x * chunk;
+  const long long c1 = min(c0 + chunk, Kc);
+  for (long long col = c0; col < c1; col += 2) {
+    const long long cg = col + g;
+    const bool ok = cg < c1;
+    float av[RPW], bv[MB];
+#pragma unroll
+    for (int a = 0; a < RPW; ++a) av[a] = ok ? abar[cg * H + 32 * (wave + 4 * a) + i] : 0.f;
+#pragma unroll
+    for (int b = 0; b < MB; ++b) bv[b] = ok ? X[cg * H + 32 * b + i] : 0.f;
+#pragma unroll
+    for (int a = 0; a < RPW; ++a)
+#pragma unroll
+      for (int b = 0; b < MB; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+  }
+  float* out = part + (long long)blockIdx.x * H * H;
+#pragma unroll
+  for (int a = 0; a < RPW; ++a)
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int o = 32 * (wave + 4 * a) + 8 * (r / 4) + 4 * g + (r % 4);
+        out[(long long)o * H + 32 * b + i] = acc[a][b][r];
+      }
+}
+
+__global__ void k_wgrad_final(const float* __restrict__ part, int nchunk, long long HH, float* __restrict__ dst) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < HH; e += (long long)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int c = 0; c < nchunk; ++c) s += part[(long long)c * HH + e];
+    dst[e] = s;
+  }
+}
+
+// Sum of adj[col] mask[col] over all columns (one block, fixed order).
+__global__ void k_masked_sum(const float* __restrict__ a, const float* __restrict__ m, long long n, float* out) {
+  __shared__ float sh[256];
+  float s = 0.f;
+  for (long long e = threadIdx.x; e < n; e += blockDim.x) s = fmaf(a[e], m[e], s);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
 // ------------------------------------------------------------------ launchers
+
+hipError_t launch_colreduce(const float* M, int H, long long Kc, const float* w, int R, int chunk, float* part,
+                            const ColDst& dst, hipStream_t s) {
+  const int nchunk = (int)((Kc + chunk - 1) / chunk);
+  switch (R) {
+    case 1: hipLaunchKernelGGL(k_colreduce<1>, dim3(nchunk), dim3(256), 0, s, M, H, Kc, w, chunk, part); break;
+    case 2: hipLaunchKernelGGL(k_colreduce<2>, dim3(nchunk), dim3(256), 0, s, M, H, Kc, w, chunk, part); break;
+    case 4: hipLaunchKernelGGL(k_colreduce<4>, dim3(nchunk), dim3(256), 0, s, M, H, Kc, w, chunk, part); break;
+    case 5: hipLaunchKernelGGL(k_colreduce<5>, dim3(nchunk), dim3(256), 0, s, M, H, Kc, w, chunk, part); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colreduce_final, dim3((H + 255) / 256, R), dim3(256), 0, s, part, nchunk, R, H, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad(int H, const float* abar, const float* X, long long Kc, int chunk, float* part, float* dst,
+                        hipStream_t s) {
+  const int nchunk = (int)((Kc + chunk - 1) / chunk);
+  switch (H) {
+    case 32: hipLaunchKernelGGL(k_wgrad<32>, dim3(nchunk), dim3(256), 0, s, abar, X, Kc, chunk, part); break;
+    case 64: hipLaunchKernelGGL(k_wgrad<64>, dim3(nchunk), dim3(256), 0, s, abar, X, Kc, chunk, part); break;
+    case 128: hipLaunchKernelGGL(k_wgrad<128>, dim3(nchunk), dim3(256), 0, s, abar, X, Kc, chunk, part); break;
+    case 256: hipLaunchKernelGGL(k_wgrad<256>, dim3(nchunk), dim3(256), 0, s, abar, X, Kc, chunk, part); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long HH = (long long)H * H;
+  hipLaunchKernelGGL(k_wgrad_final, dim3((int)std::min<long long>((HH + 255) / 256, 1024)), dim3(256), 0, s, part,
+                     nchunk, HH, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_masked_sum(const float* a, const float* m, long long n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_masked_sum, dim3(1), dim3(256), 0, s, a, m, n, out);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_fit_pack(const FitPackArgs& a, hipStream_t s) {
   const long long H = a.width, K = a.n_sine;

@@ -2,11 +2,8 @@
 // Lipschitz bounds, weight packing for the gfx950 kernels, and the launch
 // sequence of multiscale sphere tracing.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <climits>
-#include <map>
-#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -220,6 +217,7 @@ struct nnm_stack {
   int device = 0;
   int precision = 0;
   int m = 0;
+  int use_ws = 1;  // weight-stationary kernels where a level has them (NNM_NO_WS=1 disables)
   DevBase base{};
   struct Level {
     int d_in, width, n_sine, follow_center;
@@ -227,6 +225,7 @@ struct nnm_stack {
     DevLevel dev{};
     void* mem = nullptr;
     int resident[3] = {1, 1, 1};
+    int ws_resident[2] = {1, 1};
   };
   std::vector<Level> levels;
 };
@@ -356,12 +355,59 @@ static int pack_level(const nnm_level_desc& L, int precision, int device, nnm_st
       for (int r = 0; r < 16; ++r) wk[acc_slot(mb, g, r)] = L.params[wo + acc_row(mb, g, r)];
   const float bk = L.params[bo];
 
+  // Weight-stationary copy for width-256 nets with two hidden layers in
+  // bf16/fp16: wave w of a workgroup holds rows [64 w, 64 w + 64), natural K order.
+  const bool ws = (H == 256 && K == 3 && precision != NNM_PREC_FP32);
+  std::vector<float> ws_a0, bh_plain, wk_plain;
+  std::vector<uint16_t> ws_ah;
+  if (ws) {
+    ws_a0.assign(4 * 2 * 3 * 64, 0.f);
+    for (int w = 0; w < 4; ++w)
+      for (int rb = 0; rb < 2; ++rb)
+        for (int ks = 0; ks < 3; ++ks)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int row = 64 * w + 32 * rb + lane % 32, k = 2 * ks + lane / 32;
+            double v = 0.0;
+            if (k < L.d_in)
+              v = (double)W0[(size_t)row * L.d_in + k];
+            else if (k == L.d_in)
+              v = (double)b0[row];
+            ws_a0[((w * 2 + rb) * 3 + ks) * 64 + lane] = (float)(v / kTwoPiD);
+          }
+    ws_ah.assign((size_t)2 * 4 * 2 * 16 * 64 * 8, 0);
+    bh_plain.assign(2 * 256, 0.f);
+    for (int layer = 1; layer < K; ++layer) {
+      int64_t wo2, bo2;
+      layer_offsets(L.d_in, H, K, layer, &wo2, &bo2);
+      const float* W = L.params + wo2;
+      for (int row = 0; row < 256; ++row)
+        bh_plain[(layer - 1) * 256 + row] = (float)((double)L.params[bo2 + row] / kTwoPiD);
+      for (int w = 0; w < 4; ++w)
+        for (int rb = 0; rb < 2; ++rb)
+          for (int ks = 0; ks < 16; ++ks)
+            for (int lane = 0; lane < 64; ++lane)
+              for (int e = 0; e < 8; ++e) {
+                const int row = 64 * w + 32 * rb + lane % 32, col = 16 * ks + 8 * (lane / 32) + e;
+                const float v = (float)((double)W[(size_t)row * H + col] / kTwoPiD);
+                ws_ah[(((((size_t)(layer - 1) * 4 + w) * 2 + rb) * 16 + ks) * 64 + lane) * 8 + e] =
+                    precision == NNM_PREC_BF16 ? to_bf16_rne(v) : to_f16_rne(v);
+              }
+    }
+    int64_t wok, bok;
+    layer_offsets(L.d_in, H, K, K, &wok, &bok);
+    wk_plain.assign(L.params + wok, L.params + wok + 256);
+  }
+
   // One device allocation per level.
   const size_t off_a0 = 0;
   const size_t off_bh = off_a0 + align256(a0.size() * 4);
   const size_t off_wk = off_bh + align256(bh.size() * 4);
   const size_t off_ah = off_wk + align256(wk.size() * 4);
-  const size_t total = off_ah + ah.size();
+  const size_t off_ws_a0 = off_ah + align256(ah.size());
+  const size_t off_ws_ah = off_ws_a0 + align256(ws_a0.size() * 4);
+  const size_t off_bhp = off_ws_ah + align256(ws_ah.size() * 2);
+  const size_t off_wkp = off_bhp + align256(bh_plain.size() * 4);
+  const size_t total = off_wkp + align256(wk_plain.size() * 4);
   void* mem = nullptr;
   hipError_t e = hipMalloc(&mem, total);
   if (e != hipSuccess) return fail(NNM_E_NOMEM, "hipMalloc(%zu): %s", total, hipGetErrorString(e));
@@ -369,7 +415,11 @@ static int pack_level(const nnm_level_desc& L, int precision, int device, nnm_st
   if ((e = hipMemcpy(base + off_a0, a0.data(), a0.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(base + off_bh, bh.data(), bh.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(base + off_wk, wk.data(), wk.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(base + off_ah, ah.data(), ah.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+      (e = hipMemcpy(base + off_ah, ah.data(), ah.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (ws && ((e = hipMemcpy(base + off_ws_a0, ws_a0.data(), ws_a0.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+              (e = hipMemcpy(base + off_ws_ah, ws_ah.data(), ws_ah.size() * 2, hipMemcpyHostToDevice)) != hipSuccess ||
+              (e = hipMemcpy(base + off_bhp, bh_plain.data(), bh_plain.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+              (e = hipMemcpy(base + off_wkp, wk_plain.data(), wk_plain.size() * 4, hipMemcpyHostToDevice)) != hipSuccess))) {
     (void)hipFree(mem);
     return hip_fail(e, "uploading packed weights");
   }
@@ -394,7 +444,15 @@ static int pack_level(const nnm_level_desc& L, int precision, int device, nnm_st
   D.n_sine = K;
   D.follow_center = out->follow_center;
   D.reduce_hidden = hidden_arg > 64.0 ? 1 : 0;
+  if (ws) {
+    D.ws_a0 = (const float*)(base + off_ws_a0);
+    D.ws_ah = (const void*)(base + off_ws_ah);
+    D.bh_plain = (const float*)(base + off_bhp);
+    D.wk_plain = (const float*)(base + off_wkp);
+  }
   for (int kind = 0; kind < 3; ++kind) out->resident[kind] = resident_blocks(H, precision, kind, device);
+  if (ws)
+    for (int kind = 0; kind < 2; ++kind) out->ws_resident[kind] = ws_resident_blocks(precision, kind, device);
   return NNM_OK;
 }
 
@@ -420,6 +478,10 @@ int load_siren_stack(const nnm_stack_desc* d, int precision, int device, nnm_sta
   s->device = device;
   s->precision = precision;
   s->m = d->n_levels;
+  {
+    const char* no_ws = std::getenv("NNM_NO_WS");
+    s->use_ws = (no_ws && no_ws[0] == '1') ? 0 : 1;
+  }
   s->base.sphere = d->base_sphere ? 1 : 0;
   s->base.r0 = d->r0;
   s->base.rho = d->rho;
@@ -508,10 +570,16 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
     a.eps = p->eps;
     a.far = p->far;
     a.delta = is_final ? 0.f : lv.delta;
-    const long long want = ((long long)n + 127) / 128;
-    const int grid = (int)std::max(1LL, std::min(want, (long long)lv.resident[0]));
     ProfScope prof(p->profiler, 0, j, lv.width, st);
-    if ((e = launch_trace_level(lv.width, s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "trace level");
+    if (lv.dev.ws_ah && s->use_ws) {
+      const long long want = ((long long)n + kWsTileCols - 1) / kWsTileCols;
+      const int grid = (int)std::max(1LL, std::min(want, (long long)lv.ws_resident[0]));
+      if ((e = launch_trace_ws(s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "trace level (ws)");
+    } else {
+      const long long want = ((long long)n + 127) / 128;
+      const int grid = (int)std::max(1LL, std::min(want, (long long)lv.resident[0]));
+      if ((e = launch_trace_level(lv.width, s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "trace level");
+    }
   }
   if (rc == NNM_OK && normal) {
     const auto& nl = s->levels[p->normal_level];
@@ -526,10 +594,16 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
     a.queue = q[(L - 1) & 1];
     a.count = cnt + 2 * (L - 1) + 1;
     a.n = (int)n;
-    const long long want = ((long long)n + 31) / 32;
-    const int grid = (int)std::max(1LL, std::min(want, (long long)nl.resident[1]));
     ProfScope prof(p->profiler, 1, p->normal_level, nl.width, st);
-    if ((e = launch_normal(nl.width, s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "normal pass");
+    if (nl.dev.ws_ah && s->use_ws) {
+      const long long want = ((long long)n + 15) / 16;
+      const int grid = (int)std::max(1LL, std::min(want, (long long)nl.ws_resident[1]));
+      if ((e = launch_normal_ws(s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "normal pass (ws)");
+    } else {
+      const long long want = ((long long)n + 31) / 32;
+      const int grid = (int)std::max(1LL, std::min(want, (long long)nl.resident[1]));
+      if ((e = launch_normal(nl.width, s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "normal pass");
+    }
   }
   if ((e = hipFreeAsync(ws, st)) != hipSuccess && rc == NNM_OK) rc = hip_fail(e, "hipFreeAsync");
   return rc;
@@ -688,7 +762,9 @@ struct FitLayout {
   long long Kc = 0;
   int nwaves = 0;
   size_t off_a0, off_bh, off_wk, off_bk, off_ah, off_aht, off_w0t;
-  size_t off_abar, off_x, off_adj, off_mask, off_wvec, off_loss;
+  size_t off_abar, off_x, off_adj, off_mask, off_wvec, off_loss, off_part;
+  long long chunk_c = 0, chunk_w = 0;
+  int nchunk_c = 0, nchunk_w = 0;
   size_t total;
 };
 
@@ -714,29 +790,18 @@ FitLayout fit_layout(const nnm_net_shape& sh, int64_t n, int grid) {
   L.off_abar = take(K * H * (size_t)L.Kc * 4);
   L.off_x = take(K * H * (size_t)L.Kc * 4);
   L.off_adj = take((size_t)L.Kc * 4);
-  L.off_mask = take((size_t)L.Kc * 4);
-  L.off_wvec = take((size_t)sh.d_in * L.Kc * 4);
+  // mask and the d_in column-weight vectors are one contiguous [1 + d_in][Kc] block
+  L.off_mask = take((size_t)(1 + sh.d_in) * L.Kc * 4);
+  L.off_wvec = L.off_mask + (size_t)L.Kc * 4;
   L.off_loss = take((size_t)L.nwaves * 16 + 16);
+  // partial sums of the weight-gradient reductions (used one after another)
+  L.chunk_c = 2048;
+  L.nchunk_c = (int)((L.Kc + L.chunk_c - 1) / L.chunk_c);
+  L.chunk_w = std::max(64LL, ((L.Kc + 255) / 256 + 1) & ~1LL);
+  L.nchunk_w = (int)((L.Kc + L.chunk_w - 1) / L.chunk_w);
+  L.off_part = take(std::max((size_t)L.nchunk_c * 5 * H, (size_t)L.nchunk_w * H * H) * 4);
   L.total = o;
   return L;
-}
-
-std::mutex g_blas_mu;
-std::map<int, rocblas_handle> g_blas;  // one handle per device for the stateless entry points
-
-rocblas_handle blas_for_device(int device) {
-  std::lock_guard<std::mutex> lk(g_blas_mu);
-  auto it = g_blas.find(device);
-  if (it != g_blas.end()) return it->second;
-  rocblas_handle h = nullptr;
-  if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
-  rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed);
-  g_blas[device] = h;
-  return h;
-}
-
-int blas_fail(rocblas_status st, const char* what) {
-  return fail(NNM_E_DEVICE, "%s: rocBLAS status %d", what, (int)st);
 }
 
 // Packs `params` and runs the fused forward/adjoint/reverse kernel plus the
@@ -744,7 +809,7 @@ int blas_fail(rocblas_status st, const char* what) {
 int fit_backward_impl(const nnm_net_shape& sh, const float* params, int device, int grid, char* ws,
                       const FitLayout& FL, int mode, int64_t n, int64_t n_surf, const float* x0, const float* x1,
                       const float* surf_n, const float* unif_sdf, const float* dvalue, const float* dgrad,
-                      float* loss4, float* dparams, float* dx, rocblas_handle blas, hipStream_t st) {
+                      float* loss4, float* dparams, float* dx, hipStream_t st) {
   const int H = sh.width, K = sh.n_sine;
   FitPackArgs pk{};
   pk.params = params;
@@ -814,40 +879,48 @@ int fit_backward_impl(const nnm_net_shape& sh, const float* params, int device, 
   if (loss4 && mode == 0)
     if ((e = launch_fit_loss_reduce(a.loss_part, FL.nwaves, a.inv_ns, a.inv_nu, loss4, st)) != hipSuccess)
       return hip_fail(e, "loss reduce");
-  // Gradient products over the workspace: each slab is [column][neuron], i.e.
-  // a column-major H x Kc matrix with leading dimension H.
-  std::lock_guard<std::mutex> lk(g_blas_mu);
-  rocblas_status bs;
-  if ((bs = rocblas_set_stream(blas, st)) != rocblas_status_success) return blas_fail(bs, "set stream");
-  rocblas_set_pointer_mode(blas, rocblas_pointer_mode_host);
-  const float one = 1.f, zero = 0.f;
-  const int Kc = (int)FL.Kc;
+  // Gradient products over the workspace slabs ([column][neuron]), each column
+  // read once, partial sums over column chunks added in a fixed order.
+  const int d_in = sh.d_in;
   const float* abar = a.ws_abar;
   const float* X = a.ws_x;
   const size_t LS = (size_t)H * FL.Kc;  // floats per layer slab
+  float* part = (float*)(ws + FL.off_part);
   for (int i = 1; i < K; ++i) {
-    // W_i-bar[out][in] = sum_col abar_i[col][out] X_i[col][in], X_i = inputs of layer i;
-    // column-major C (in x out) = X (H x Kc) * abar^T (Kc x H).
-    bs = rocblas_sgemm(blas, rocblas_operation_none, rocblas_operation_transpose, H, H, Kc, &one, X + (i - 1) * LS, H,
-                       abar + i * LS, H, &zero, dparams + pk.w_off[i], H);
-    if (bs != rocblas_status_success) return blas_fail(bs, "hidden weight gradient");
+    // W_i-bar[out][in] = sum_col abar_i[col][out] X_i[col][in], X_i = inputs of layer i
+    if ((e = launch_wgrad(H, abar + i * LS, X + (i - 1) * LS, FL.Kc, (int)FL.chunk_w, part, dparams + pk.w_off[i],
+                          st)) != hipSuccess)
+      return hip_fail(e, "hidden weight gradient");
   }
-  for (int i = 0; i < K; ++i) {
-    bs = rocblas_sgemv(blas, rocblas_operation_none, H, Kc, &one, abar + i * LS, H, va.mask, 1, &zero,
-                       dparams + pk.b_off[i], 1);
-    if (bs != rocblas_status_success) return blas_fail(bs, "bias gradient");
+  // layer 0: b_0-bar (primal mask) and W_0-bar[:, j] (column weights w_j); the
+  // mask and the w_j are contiguous vectors of length Kc in the workspace.
+  {
+    ColDst dst{};
+    dst.ptr[0] = dparams + pk.b_off[0];
+    dst.stride[0] = 1;
+    for (int j = 0; j < d_in; ++j) {
+      dst.ptr[1 + j] = dparams + pk.w_off[0] + j;
+      dst.stride[1 + j] = d_in;
+    }
+    if ((e = launch_colreduce(abar, H, FL.Kc, va.mask, 1 + d_in, (int)FL.chunk_c, part, dst, st)) != hipSuccess)
+      return hip_fail(e, "first-layer gradient");
   }
-  // W_0-bar[out][j] = sum_col abar_0[col][out] w_j[col]; column-major C (d_in x out).
-  bs = rocblas_sgemm(blas, rocblas_operation_transpose, rocblas_operation_transpose, sh.d_in, H, Kc, &one, va.wvec,
-                     Kc, abar, H, &zero, dparams + pk.w_off[0], sh.d_in);
-  if (bs != rocblas_status_success) return blas_fail(bs, "first-layer gradient");
-  bs = rocblas_sgemv(blas, rocblas_operation_none, H, Kc, &one, X + (K - 1) * LS, H, a.adj, 1, &zero,
-                     dparams + pk.w_off[K], 1);
-  if (bs != rocblas_status_success) return blas_fail(bs, "output-layer gradient");
-  rocblas_set_pointer_mode(blas, rocblas_pointer_mode_device);
-  bs = rocblas_sdot(blas, Kc, a.adj, 1, va.mask, 1, dparams + pk.b_off[K]);
-  rocblas_set_pointer_mode(blas, rocblas_pointer_mode_host);
-  if (bs != rocblas_status_success) return blas_fail(bs, "output-bias gradient");
+  for (int i = 1; i < K; ++i) {
+    ColDst dst{};
+    dst.ptr[0] = dparams + pk.b_off[i];
+    dst.stride[0] = 1;
+    if ((e = launch_colreduce(abar + i * LS, H, FL.Kc, va.mask, 1, (int)FL.chunk_c, part, dst, st)) != hipSuccess)
+      return hip_fail(e, "bias gradient");
+  }
+  {
+    ColDst dst{};
+    dst.ptr[0] = dparams + pk.w_off[K];
+    dst.stride[0] = 1;
+    if ((e = launch_colreduce(X + (K - 1) * LS, H, FL.Kc, a.adj, 1, (int)FL.chunk_c, part, dst, st)) != hipSuccess)
+      return hip_fail(e, "output-layer gradient");
+  }
+  if ((e = launch_masked_sum(a.adj, va.mask, FL.Kc, dparams + pk.b_off[K], st)) != hipSuccess)
+    return hip_fail(e, "output-bias gradient");
   return NNM_OK;
 }
 
@@ -866,7 +939,6 @@ struct nnm_fit {
   float* state = nullptr;  // params | m | v | grad
   char* ws = nullptr;
   FitLayout layout{};
-  rocblas_handle blas = nullptr;
   int64_t step = 0;
 };
 
@@ -958,10 +1030,8 @@ int siren_backward(const nnm_net_shape* shape, const float* params, int64_t n, c
   const FitLayout FL = fit_layout(*shape, n, grid);
   if (!workspace || workspace_bytes < (int64_t)FL.total)
     return fail(NNM_E_INVAL, "workspace of %lld bytes, %zu needed", (long long)workspace_bytes, FL.total);
-  rocblas_handle h = blas_for_device(dev);
-  if (!h) return fail(NNM_E_DEVICE, "rocblas handle");
   return fit_backward_impl(*shape, params, dev, grid, (char*)workspace, FL, 1, n, 0, x, nullptr, nullptr, nullptr,
-                           dvalue, dgrad, nullptr, dparams, dx, h, (hipStream_t)stream);
+                           dvalue, dgrad, nullptr, dparams, dx, (hipStream_t)stream);
 }
 
 int fit_create(const nnm_net_shape* shape, const float* params, int device, int64_t max_points, nnm_fit** out) {
@@ -996,11 +1066,6 @@ int fit_create(const nnm_net_shape* shape, const float* params, int device, int6
     fit_free(f);
     return hip_fail(e, "fit upload");
   }
-  if (rocblas_create_handle(&f->blas) != rocblas_status_success) {
-    fit_free(f);
-    return fail(NNM_E_DEVICE, "rocblas handle");
-  }
-  rocblas_set_atomics_mode(f->blas, rocblas_atomics_not_allowed);
   *out = f;
   return NNM_OK;
 }
@@ -1008,7 +1073,6 @@ int fit_create(const nnm_net_shape* shape, const float* params, int device, int6
 void fit_free(nnm_fit* f) {
   if (!f) return;
   DeviceGuard guard(f->device);
-  if (f->blas) rocblas_destroy_handle(f->blas);
   if (f->state) (void)hipFree(f->state);
   if (f->ws) (void)hipFree(f->ws);
   delete f;
@@ -1035,7 +1099,7 @@ int fit_loss_grad(nnm_fit* f, const nnm_fit_batch* b, float* loss4, float* dpara
   const int64_t n = b->n_surf + b->n_unif;
   const FitLayout FL = fit_layout(f->shape, n, f->grid);
   return fit_backward_impl(f->shape, f->state, f->device, f->grid, f->ws, FL, 0, n, b->n_surf, b->surf_x, b->unif_x,
-                           b->surf_n, b->unif_sdf, nullptr, nullptr, loss4, dparams, nullptr, f->blas,
+                           b->surf_n, b->unif_sdf, nullptr, nullptr, loss4, dparams, nullptr,
                            (hipStream_t)stream);
 }
 
@@ -1057,7 +1121,7 @@ int fit_step(nnm_fit* f, const nnm_fit_batch* b, const nnm_adam* opt, float* los
   const FitLayout FL = fit_layout(f->shape, n, f->grid);
   hipStream_t st = (hipStream_t)stream;
   rc = fit_backward_impl(f->shape, params, f->device, f->grid, f->ws, FL, 0, n, b->n_surf, b->surf_x, b->unif_x,
-                         b->surf_n, b->unif_sdf, nullptr, nullptr, loss4, grad, nullptr, f->blas, st);
+                         b->surf_n, b->unif_sdf, nullptr, nullptr, loss4, grad, nullptr, st);
   if (rc != NNM_OK) return rc;
   const int64_t t = f->step + 1;
   const double bc1 = 1.0 - std::pow((double)opt->beta1, (double)t);

@@ -31,6 +31,7 @@ constexpr int kChunk = 256;         // most queue entries a wave takes per atomi
 constexpr int kPushBatch = 64;      // queue entries a wave publishes per atomic
 constexpr int kSegments = 64;       // input queue segments, each with its own head
 constexpr int kHeadStride = 32;     // ints between segment heads (one 128-byte line each)
+constexpr int kWsTileCols = 64;     // columns per weight-stationary workgroup tile
 
 // Index of the accumulator-layout slot (mb, g, r) in a [H] array.
 __host__ __device__ inline int acc_slot(int mb, int g, int r) { return (mb * 2 + g) * 16 + r; }
@@ -66,6 +67,11 @@ struct DevLevel {
   int n_sine;
   int follow_center;
   int reduce_hidden;  // 1: reduce hidden sine arguments with fract first
+  // Weight-stationary layout (width 256, two hidden layers, bf16/fp16), or null:
+  const float* ws_a0;     // [4 waves][2 row blocks][3 k-steps][64 lanes] layer-0 A / 2pi
+  const void* ws_ah;      // [2 layers][4 waves][2 row blocks][16 k-steps][64 lanes] 16-byte A fragments
+  const float* bh_plain;  // [2][256] hidden biases / 2pi, row order
+  const float* wk_plain;  // [256] output weights, row order
 };
 
 struct DevBase {

@@ -121,10 +121,24 @@ hipError_t launch_adam(float* params, const float* grad, float* m, float* v, lon
                        float b2, float eps, float bc1, float bc2, hipStream_t s);
 int fit_fb_grid(int width, int device);
 
+// Destinations of a column reduction: row `row` of vector r goes to ptr[r][row * stride[r]].
+struct ColDst {
+  float* ptr[5];
+  long long stride[5];
+};
+hipError_t launch_colreduce(const float* M, int H, long long Kc, const float* w, int R, int chunk, float* part,
+                            const ColDst& dst, hipStream_t s);
+hipError_t launch_wgrad(int H, const float* abar, const float* X, long long Kc, int chunk, float* part, float* dst,
+                        hipStream_t s);
+hipError_t launch_masked_sum(const float* a, const float* m, long long n, float* out, hipStream_t s);
+
 hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
 hipError_t launch_trace_level(int width, int prec, const TraceLevelArgs& a, int grid, hipStream_t s);
 hipError_t launch_normal(int width, int prec, const NormalArgs& a, int grid, hipStream_t s);
 hipError_t launch_points(int width, int prec, const PointsArgs& a, int grid, hipStream_t s);
+hipError_t launch_trace_ws(int prec, const TraceLevelArgs& a, int grid, hipStream_t s);
+hipError_t launch_normal_ws(int prec, const NormalArgs& a, int grid, hipStream_t s);
+int ws_resident_blocks(int prec, int kind, int device);  // kind: 0 trace, 1 normal
 // Workgroups of each kernel kind that fit on the whole device at once.
 int resident_blocks(int width, int prec, int kind, int device);  // kind: 0 trace, 1 normal, 2 points
 

@@ -1,0 +1,26 @@
+// trace_common.h -- device helpers shared by the tracing kernels.
+#pragma once
+#include "nnm_kernels.h"
+#include "siren_tile.h"
+
+namespace nnm {
+
+// Network input of a level: (x, t) for 4-D nets, x - c(t) for nets that move
+// with the centre, else x.
+__device__ inline float4 net_input(const DevLevel& L, float x, float y, float z, float t, float cx, float cy) {
+  if (L.d_in == 4) return make_float4(x, y, z, t);
+  if (L.follow_center) return make_float4(x - cx, y - cy, z, 0.f);
+  return make_float4(x, y, z, 0.f);
+}
+
+__device__ inline void center_at(const DevBase& B, float t, float& cx, float& cy) {
+  cx = 0.f;
+  cy = 0.f;
+  if (B.rho != 0.f) {
+    const float tr = fract_rev(t);
+    cx = B.rho * cos_rev(tr);
+    cy = B.rho * sin_rev(tr);
+  }
+}
+
+}  // namespace nnm

@@ -11,26 +11,9 @@
 // on the next iteration, so tiles stay dense while the queue lasts and every
 // tile evaluates one network only.  The normal pass then evaluates the normal
 // level's forward and three tangent columns (Sec. 5.1) at the hit points.
-#include "nnm_kernels.h"
-#include "siren_tile.h"
+#include "trace_common.h"
 
 namespace nnm {
-
-__device__ inline float4 net_input(const DevLevel& L, float x, float y, float z, float t, float cx, float cy) {
-  if (L.d_in == 4) return make_float4(x, y, z, t);
-  if (L.follow_center) return make_float4(x - cx, y - cy, z, 0.f);
-  return make_float4(x, y, z, 0.f);
-}
-
-__device__ inline void center_at(const DevBase& B, float t, float& cx, float& cy) {
-  cx = 0.f;
-  cy = 0.f;
-  if (B.rho != 0.f) {
-    const float tr = fract_rev(t);
-    cx = B.rho * cos_rev(tr);
-    cy = B.rho * sin_rev(tr);
-  }
-}
 
 __global__ void k_zero_ints(int* p, int count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

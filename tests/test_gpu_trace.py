@@ -170,3 +170,21 @@ def test_edge_cases():
         nnm.render(stack, torch.zeros((4, 3), device=dev), torch.zeros((4, 3), device=dev),
                    params=nnm.TraceParams(max_steps=0))
     stack.close()
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_weight_stationary_matches_streaming(precision, monkeypatch):
+    """The (256,2) level runs the weight-stationary kernels in bf16/fp16; the
+    streaming kernels (NNM_NO_WS=1) compute the same sums in another K order."""
+    s = ni.make_scene("stack3_512sq").with_size(384, 256)
+    o, v, _ = s.rays()
+    ws = gpu_trace(s, o, v, precision=precision)
+    monkeypatch.setenv("NNM_NO_WS", "1")
+    st = gpu_trace(s, o, v, precision=precision)
+    monkeypatch.delenv("NNM_NO_WS")
+    both = (ws["hit"] == 1) & (st["hit"] == 1)
+    assert np.mean(ws["hit"] == st["hit"]) >= 0.9995
+    assert np.abs(ws["depth"][both] - st["depth"][both]).max() <= 2e-4
+    assert angle_deg(ws["normal"][both], st["normal"][both]).mean() <= 0.01
+    r = orc.trace(s, o, v)
+    check_lowp(compare(ws, r))
