@@ -572,7 +572,7 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
     a.delta = is_final ? 0.f : lv.delta;
     ProfScope prof(p->profiler, 0, j, lv.width, st);
     if (lv.dev.ws_ah && s->use_ws) {
-      const long long want = ((long long)n + kWsTileCols - 1) / kWsTileCols;
+      const long long want = ((long long)n + kWsRaysPerBlock - 1) / kWsRaysPerBlock;
       const int grid = (int)std::max(1LL, std::min(want, (long long)lv.ws_resident[0]));
       if ((e = launch_trace_ws(s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "trace level (ws)");
     } else {
@@ -596,7 +596,7 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
     a.n = (int)n;
     ProfScope prof(p->profiler, 1, p->normal_level, nl.width, st);
     if (nl.dev.ws_ah && s->use_ws) {
-      const long long want = ((long long)n + 15) / 16;
+      const long long want = ((long long)n + kWsPointsPerBlock - 1) / kWsPointsPerBlock;
       const int grid = (int)std::max(1LL, std::min(want, (long long)nl.ws_resident[1]));
       if ((e = launch_normal_ws(s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "normal pass (ws)");
     } else {

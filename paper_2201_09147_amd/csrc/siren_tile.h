@@ -157,21 +157,34 @@ struct SirenTile {
   // h = sin(a) for primal columns; G = 2 pi v cos(a) for tangent columns, a the
   // primal accumulator of the same quad.  Accumulators are in revolutions
   // (weights / 2 pi); tangent accumulators carry (W / 2 pi) G, hence the 2 pi.
-  __device__ inline void activate(const f32x16_t* acc, int c, bool reduce) {
+  //
+  // One sine per element: cos(2 pi r) = sin(2 pi (r + 1/4)), so tangent lanes
+  // shift the argument by a quarter revolution and scale by 2 pi v.  RED adds
+  // the reduction to [0, 1) revolutions (first layer, or wide argument bounds).
+  template <bool RED>
+  __device__ inline void activate_r(const f32x16_t* acc, int c) {
+    const float off = c ? 0.25f : 0.f, m1 = c ? kTwoPi : 0.f, m0 = c ? 0.f : 1.f;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const float v = acc[mb][r];
         if (TAN) {
-          float rp = quad_bcast<0>(v);
-          if (reduce) rp = fract_rev(rp);
-          const float sv = sin_rev(rp), cv = cos_rev(rp);
-          act[mb][r] = (c == 0) ? sv : (kTwoPi * v) * cv;
+          float rp = quad_bcast<0>(v) + off;
+          if (RED) rp = fract_rev(rp);
+          act[mb][r] = sin_rev(rp) * fmaf(v, m1, m0);
         } else {
-          act[mb][r] = sin_rev(reduce ? fract_rev(v) : v);
+          act[mb][r] = sin_rev(RED ? fract_rev(v) : v);
         }
       }
+  }
+
+  // reduce is uniform (per level): a branch, not a per-element select
+  __device__ inline void activate(const f32x16_t* acc, int c, bool reduce) {
+    if (reduce)
+      activate_r<true>(acc, c);
+    else
+      activate_r<false>(acc, c);
   }
 
   // Layer-0 accumulators: W_0 [in | 1] / 2 pi (tangent columns: W_0[:, c-1] / 2 pi).

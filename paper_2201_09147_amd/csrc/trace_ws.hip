@@ -1,430 +1,614 @@
-// trace_ws.hip -- weight-stationary tracing and normal kernels for width-256
-// networks with two hidden layers in bf16 / fp16 (the fine level of the
-// nested stacks).
+// trace_ws.hip -- pipelined weight-stationary tracing and normal kernels for
+// width-256 networks with two hidden layers in bf16 / fp16 (the fine level of
+// the nested stacks).
 //
-// A workgroup is four waves, one per SIMD.  Wave w keeps rows [64 w, 64 w + 64)
-// of both hidden weight matrices in registers for the whole kernel (2 x 32 KB
-// per wave), so the hidden weights are read from memory once per workgroup
-// instead of once per tile.  A tile is 64 columns (64 rays, or 16 points x
-// [h | G_x G_y G_z] in the normal pass).  Each layer:
-//   * every wave multiplies its 64 rows by all 256 inputs of the 64 columns
-//     (32x32x16 MFMAs: A = its stationary weights, B = the previous layer's
-//     activations read from LDS, C = the bias);
-//   * applies sin (revolutions) to its rows and writes them, as 16-bit values,
-//     into the LDS activation buffer of the next layer;
-//   * a barrier publishes the rows to the other waves.
-// Layer 0 is a 32x32x2 fp32 MFMA over (x, y, z[, t], 1) per wave; the last
-// layer's activations stay in float32 and feed the output dot product as
-// per-wave partial sums combined through LDS.  Wave 0 runs the sphere-tracing
-// control (slot refill from the segmented queue, the Algorithm 1 update,
-// compaction into the next queue) on 64 slots, one per lane.
+// A workgroup is eight waves in two teams, one workgroup per CU, and every SIMD
+// holds one wave of each team (roles are assigned from the SIMD each wave runs
+// on).  Team 1 (waves 0-3) keeps rows [64 w, 64 w + 64)
+// of the first hidden weight matrix in registers for the whole kernel, team 2
+// (waves 4-7) the same rows of the second; the hidden weights are read from
+// memory once per workgroup.  Tiles of 32 columns (32 rays, or 8 points x
+// [h | G_x G_y G_z] for the normal) move through a software pipeline with one
+// workgroup barrier per stage.  In stage s:
+//   * every wave evaluates its 32-row block of the first sine layer of tile s
+//     (32x32x2 fp32 MFMA over (x, y, z[, t], 1), then sin) into act0[s % 2];
+//   * team 1 multiplies tile s-1 (act0) by its rows of W_1 (32x32x16 MFMAs,
+//     B operand from LDS, C initialised with the bias), applies sin and writes
+//     the 16-bit activations to act1[(s-1) % 2]: MFMA first, then VALU;
+//   * team 2 applies sin to its accumulators of tile s-3 and forms its part of
+//     the output dot product, then multiplies tile s-2 (act1) by its rows of
+//     W_2: VALU first, then MFMA (its first wave runs the control step between
+//     the two, while its accumulators are free);
+//   * one team-2 wave takes the outputs of tile s-4, runs the Algorithm 1 update (or
+//     the normal's last step), retires finished rays, refills the freed slots
+//     and writes the inputs of tile s+1.
+// The two teams' MFMA and VALU phases are opposite, so each SIMD overlaps one
+// wave's matrix work with the other's sines.  Tile t occupies slot group
+// t % kPipeGroups; the ray state of a group waits in LDS while its tile is in
+// flight.  Activations are exchanged in natural row order, so these kernels use
+// the row-split fragments of the weight-stationary pack, not the K permutation
+// of the single-wave tiles.
 #include "trace_common.h"
 
 namespace nnm {
 
-constexpr int kWsCols = 64;         // columns per workgroup tile
-constexpr int kWsStride = 256 + 8;  // 16-bit elements per LDS column (padding spreads LDS banks)
+constexpr int kPipeThreads = 512;
+constexpr int kPipeCols = 32;         // columns per tile
+constexpr int kPipeStride = 256 + 8;  // 16-bit elements per LDS column (spreads LDS banks)
+static_assert(kPipeGroups == 5, "tile t uses group t % 5: five tiles are in flight");
+static_assert(kPipeGroups * kPipeCols == kWsRaysPerBlock && kPipeGroups * 8 == kWsPointsPerBlock, "slots");
 
-struct WsSmem {
-  uint16_t act[2][kWsCols * kWsStride];
+struct PipeSmem {
+  uint16_t act0[2][kPipeCols * kPipeStride];
+  uint16_t act1[2][kPipeCols * kPipeStride];
   float bias[2][256];
+  float zeros[256];
   float wk[256];
-  float part[4][kWsCols];
-  float4 xin[kWsCols];
-  int flag;
+  float part[2][4][kPipeCols];
+  float4 xin[2][kPipeCols];
+  int sray[kPipeGroups][kPipeCols];
+  int sk[kPipeGroups][kPipeCols];
+  int sst[kPipeGroups][kPipeCols];
+  float sf[8][kPipeGroups][kPipeCols];
+  int tlive[8];
+  int glive[kPipeGroups];
+  int stop[2];
+  int simd_count[4];
+  int role_of[8];
   int ring[2 * kPushBatch];
 };
 
 template <int P>
-struct WsBits;
+struct PipeBits;
 template <>
-struct WsBits<PREC_BF16> {
-  static __device__ inline uint16_t bits(float v) {
-    const __bf16 h = (__bf16)v;
-    return __builtin_bit_cast(uint16_t, h);
-  }
+struct PipeBits<PREC_BF16> {
+  static __device__ inline uint16_t bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 };
 template <>
-struct WsBits<PREC_FP16> {
-  static __device__ inline uint16_t bits(float v) {
-    const _Float16 h = (_Float16)v;
-    return __builtin_bit_cast(uint16_t, h);
-  }
+struct PipeBits<PREC_FP16> {
+  static __device__ inline uint16_t bits(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
 };
 
-// Stationary state of one wave: its rows of the layer-0 A operand and of both
-// hidden weight matrices.
+// Per-lane roles.  TAN: column j = 4 q + c is point q's primal (c = 0) or
+// tangent c column; the activation is sin(2 pi r) on primal columns and
+// (2 pi v) cos(2 pi r) = (2 pi v) sin(2 pi (r + 1/4)) on tangent columns, r the
+// quad's primal pre-activation: one sine and one fma per element.
+struct PipeLane {
+  int j, g, c;
+  float off, m1, m0;
+};
+
+template <bool TAN>
+__device__ inline PipeLane pipe_lane(int lane) {
+  PipeLane p;
+  p.j = lane & 31;
+  p.g = lane >> 5;
+  p.c = TAN ? (p.j & 3) : 0;
+  p.off = p.c ? 0.25f : 0.f;
+  p.m1 = p.c ? kTwoPi : 0.f;
+  p.m0 = p.c ? 0.f : 1.f;
+  return p;
+}
+
+template <bool TAN, bool RED>
+__device__ inline float pipe_act(float v, const PipeLane& pl) {
+  if (TAN) {
+    float r = quad_bcast<0>(v) + pl.off;
+    if (RED) r = fract_rev(r);
+    return sin_rev(r) * fmaf(v, pl.m1, pl.m0);
+  }
+  return sin_rev(RED ? fract_rev(v) : v);
+}
+
+// Stationary registers of one wave: its 32-row block of the layer-0 operand
+// and its 64 rows of its team's hidden matrix.
 template <int P>
-struct WsWeights {
+struct PipeWeights {
   typedef typename HiddenOps<P>::frag_t frag_t;
-  float w0[2][3];
-  frag_t w1[2][16];
-  frag_t w2[2][16];
+  float w0[3];
+  frag_t w[2][16];
 
   __device__ inline void load(const DevLevel& L, int wave, int lane) {
+    const int team = wave >> 2, tw = wave & 3;
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int ks = 0; ks < 3; ++ks) w0[rb][ks] = L.ws_a0[((wave * 2 + rb) * 3 + ks) * 64 + lane];
+    for (int ks = 0; ks < 3; ++ks) w0[ks] = L.ws_a0[(wave * 3 + ks) * 64 + lane];
     const frag_t* WA = (const frag_t*)L.ws_ah;
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int ks = 0; ks < 16; ++ks) {
-        w1[rb][ks] = WA[(((0 * 4 + wave) * 2 + rb) * 16 + ks) * 64 + lane];
-        w2[rb][ks] = WA[(((1 * 4 + wave) * 2 + rb) * 16 + ks) * 64 + lane];
-      }
+      for (int ks = 0; ks < 16; ++ks) w[rb][ks] = WA[(((team * 4 + tw) * 2 + rb) * 16 + ks) * 64 + lane];
+    // wait here for every weight (vmcnt 0): otherwise the first uses inside the
+    // stage loop carry waits that also cover the control wave's prefetches
+    __builtin_amdgcn_s_waitcnt(0x0F70);
   }
 };
 
-__device__ inline int ws_row(int wave, int rb, int g, int r) { return 64 * wave + 32 * rb + 8 * (r / 4) + 4 * g + (r % 4); }
+__device__ inline void pipe_store4(uint16_t* dst, uint16_t h0, uint16_t h1, uint16_t h2, uint16_t h3) {
+  uint2 packed;
+  packed.x = (uint32_t)h0 | ((uint32_t)h1 << 16);
+  packed.y = (uint32_t)h2 | ((uint32_t)h3 << 16);
+  *(uint2*)dst = packed;
+}
 
-// One wave's part of a tile evaluation.  TAN: columns 4q+c are [h | G].
-// Returns, per lane and column block, this wave's partial output sum.
+// First sine layer, rows [32 wave, 32 wave + 32) of one tile.
 template <int P, bool TAN>
-__device__ inline void ws_eval(WsSmem& sm, const WsWeights<P>& W, const DevLevel& L, float part[2]) {
-  typedef HiddenOps<P> Ops;
-  typedef typename Ops::frag_t frag_t;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 31, g = lane >> 5;
-  const int c = j & 3;  // column role in the tangent mode
-  const int ks0 = L.d_in == 4 ? 3 : 2;
-  f32x16_t acc[2][2];
-  // ---- layer 0 (fp32 MFMA over the augmented input)
+__device__ inline void pipe_layer0(const PipeWeights<P>& W, const float4* xin, uint16_t* dst, int d_in, int wave,
+                                   const PipeLane& pl) {
+  const float4 in = xin[pl.j];
+  const int ks0 = d_in == 4 ? 3 : 2;
+  f32x16_t acc;
 #pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
-    const float4 in = sm.xin[32 * cb + j];
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
+  for (int ks = 0; ks < 3; ++ks)
+    if (ks < ks0)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(W.w0[ks], layer0_input(in, d_in, pl.c, ks, pl.g), acc, 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[cb][rb][r] = 0.f;
+  for (int b4 = 0; b4 < 4; ++b4) {
+    uint16_t h[4];
 #pragma unroll
-      for (int ks = 0; ks < 3; ++ks)
-        if (ks < ks0)
-          acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(W.w0[rb][ks], layer0_input(in, L.d_in, TAN ? c : 0, ks, g),
-                                                             acc[cb][rb], 0, 0, 0);
-    }
-  }
-  // ---- three activations: layer 0 -> act[0], hidden 1 -> act[1], hidden 2 -> output
-#pragma unroll
-  for (int stage = 0; stage < 3; ++stage) {
-    if (stage > 0) {
-      const uint16_t* src = sm.act[stage - 1];
-      const float* bias = sm.bias[stage - 1];
-      const bool primal = !TAN || c == 0;
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) acc[cb][rb][r] = primal ? bias[ws_row(wave, rb, g, r)] : 0.f;
-#pragma unroll
-      for (int ks = 0; ks < 16; ++ks) {
-        frag_t b[2];
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) b[cb] = *(const frag_t*)&src[(32 * cb + j) * kWsStride + 16 * ks + 8 * g];
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-          for (int rb = 0; rb < 2; ++rb)
-            acc[cb][rb] = Ops::mfma(stage == 1 ? W.w1[rb][ks] : W.w2[rb][ks], b[cb], acc[cb][rb]);
-      }
-    }
-    const bool reduce = stage == 0 || L.reduce_hidden;
-    if (stage < 2) {
-      uint16_t* dst = sm.act[stage];
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-          for (int b4 = 0; b4 < 4; ++b4) {
-            uint16_t h[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const float v = acc[cb][rb][4 * b4 + i];
-              float a;
-              if (TAN) {
-                // one sine per lane: sin(2 pi r) on primal columns, cos(2 pi r) =
-                // sin(2 pi (r + 1/4)) on tangent columns (r reduced to [0, 1) first)
-                const float rp = fract_rev(quad_bcast<0>(v));
-                const float sv = sin_rev(c == 0 ? rp : rp + 0.25f);
-                a = (c == 0) ? sv : (kTwoPi * v) * sv;
-              } else {
-                a = sin_rev(reduce ? fract_rev(v) : v);
-              }
-              h[i] = WsBits<P>::bits(a);
-            }
-            const int row = 64 * wave + 32 * rb + 8 * b4 + 4 * g;
-            uint2 packed;
-            packed.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-            packed.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-            *(uint2*)&dst[(32 * cb + j) * kWsStride + row] = packed;
-          }
-      __syncthreads();
-    } else {
-      // last hidden layer: float32 activations into the output dot product
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        float s = 0.f;
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const float v = acc[cb][rb][r];
-            float a;
-            if (TAN) {
-              const float rp = fract_rev(quad_bcast<0>(v));
-              const float sv = sin_rev(c == 0 ? rp : rp + 0.25f);
-              a = (c == 0) ? sv : (kTwoPi * v) * sv;
-            } else {
-              a = sin_rev(reduce ? fract_rev(v) : v);
-            }
-            s = fmaf(sm.wk[ws_row(wave, rb, g, r)], a, s);
-          }
-        part[cb] = s + __shfl_xor(s, 32);
-      }
-    }
+    for (int i = 0; i < 4; ++i) h[i] = PipeBits<P>::bits(pipe_act<TAN, true>(acc[4 * b4 + i], pl));
+    pipe_store4(&dst[pl.j * kPipeStride + 32 * wave + 8 * b4 + 4 * pl.g], h[0], h[1], h[2], h[3]);
   }
 }
 
+// Hidden product of one team wave: acc = bias + W[rows] act (the caller passes
+// a zero bias for tangent columns).
 template <int P>
-__global__ void __launch_bounds__(kBlockThreads, 1) k_trace_ws(TraceLevelArgs A) {
-  __shared__ WsSmem sm;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = (lane >> 5);
-  const DevLevel& L = A.L;
-  WsWeights<P> W;
-  W.load(L, wave, lane);
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+__device__ inline void pipe_hidden(const PipeWeights<P>& W, const uint16_t* src, const float* bias, f32x16_t (&acc)[2],
+                                   int tw, const PipeLane& pl) {
+  typedef HiddenOps<P> Ops;
+  typedef typename Ops::frag_t frag_t;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int b4 = 0; b4 < 4; ++b4) {
+      const float4 b = *(const float4*)&bias[64 * tw + 32 * rb + 8 * b4 + 4 * pl.g];
+      acc[rb][4 * b4 + 0] = b.x;
+      acc[rb][4 * b4 + 1] = b.y;
+      acc[rb][4 * b4 + 2] = b.z;
+      acc[rb][4 * b4 + 3] = b.w;
+    }
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) {
+    const frag_t b = *(const frag_t*)&src[pl.j * kPipeStride + 16 * ks + 8 * pl.g];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) acc[rb] = Ops::mfma(W.w[rb][ks], b, acc[rb]);
+  }
+}
+
+// sin of a team-1 wave's rows into the next layer's activations.
+template <int P, bool TAN, bool RED>
+__device__ inline void pipe_store(const f32x16_t (&acc)[2], uint16_t* dst, int tw, const PipeLane& pl) {
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int b4 = 0; b4 < 4; ++b4) {
+      uint16_t h[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[i] = PipeBits<P>::bits(pipe_act<TAN, RED>(acc[rb][4 * b4 + i], pl));
+      pipe_store4(&dst[pl.j * kPipeStride + 64 * tw + 32 * rb + 8 * b4 + 4 * pl.g], h[0], h[1], h[2], h[3]);
+    }
+}
+
+// sin of a team-2 wave's rows, dotted with the output weights in float32.
+template <bool TAN, bool RED>
+__device__ inline float pipe_dot(const f32x16_t (&acc)[2], const float* wk, int tw, const PipeLane& pl) {
+  float s = 0.f;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int b4 = 0; b4 < 4; ++b4) {
+      const float4 w = *(const float4*)&wk[64 * tw + 32 * rb + 8 * b4 + 4 * pl.g];
+      s = fmaf(w.x, pipe_act<TAN, RED>(acc[rb][4 * b4 + 0], pl), s);
+      s = fmaf(w.y, pipe_act<TAN, RED>(acc[rb][4 * b4 + 1], pl), s);
+      s = fmaf(w.z, pipe_act<TAN, RED>(acc[rb][4 * b4 + 2], pl), s);
+      s = fmaf(w.w, pipe_act<TAN, RED>(acc[rb][4 * b4 + 3], pl), s);
+    }
+  return s + __shfl_xor(s, 32);
+}
+
+__device__ inline void pipe_setup(PipeSmem& sm, const DevLevel& L) {
+  for (int i = threadIdx.x; i < 256; i += kPipeThreads) {
     sm.bias[0][i] = L.bh_plain[i];
     sm.bias[1][i] = L.bh_plain[256 + i];
     sm.wk[i] = L.wk_plain[i];
+    sm.zeros[i] = 0.f;
+  }
+  for (int i = threadIdx.x; i < kPipeGroups * kPipeCols; i += kPipeThreads) (&sm.sray[0][0])[i] = -1;
+  if (threadIdx.x < 8) sm.tlive[threadIdx.x] = 0;
+  if (threadIdx.x < kPipeGroups) sm.glive[threadIdx.x] = 0;
+  if (threadIdx.x < 2) sm.stop[threadIdx.x] = 0;
+  if (threadIdx.x < 4) sm.simd_count[threadIdx.x] = 0;
+}
+
+// Role of this wave, 4 team + simd: the first wave that arrives on a SIMD joins
+// team 1, the second team 2, so every SIMD pairs one wave of each team whatever
+// placement the dispatcher chose.  (Eight waves of 256 registers fill the four
+// register files exactly, so each SIMD holds two of them; if the counts say
+// otherwise the wave index decides.)  Contains a workgroup barrier.
+__device__ inline int pipe_role(PipeSmem& sm) {
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    // HW_ID bits [5:4]: the SIMD this wave runs on
+    const int simd = (__builtin_amdgcn_s_getreg((1 << 11) | (4 << 6) | 4)) & 3;
+    const int slot = atomicAdd(&sm.simd_count[simd], 1);
+    sm.role_of[wave] = 4 * slot + simd;
   }
   __syncthreads();
-  // Wave 0: one slot per lane; a 64-entry staging ring of prefetched rays
-  // (lane e holds ring entry e) refills empty slots through lane shuffles, and
-  // is topped up right after, so its loads complete during the evaluation.
-  const int n_in = A.in_count ? *A.in_count : A.n;
-  int ray = -1, k = 0, st = 0;
-  float tau = 0.f, ox = 0.f, oy = 0.f, oz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, tt = 0.f, x = 0.f, y = 0.f, z = 0.f,
-        cx = 0.f, cy = 0.f;
-  int s_ray = -1, s_st = 0;
-  float s_ox = 0.f, s_oy = 0.f, s_oz = 0.f, s_vx = 0.f, s_vy = 0.f, s_vz = 0.f, s_tt = 0.f, s_tau = 0.f;
-  int s_head = 0, s_count = 0;
-  int cur = 0, end = 0, ring_start = 0, ring_n = 0;
-  const int chunk = min(kChunk, max(64, (n_in / (8 * (int)gridDim.x)) & ~63));
-  const int seg_len = (n_in + kSegments - 1) / kSegments;
-  int seg = blockIdx.x % kSegments, seg_tries = 0;
-  bool exhausted = false;
-  for (;;) {
-    if (wave == 0) {
-      bool live;
-      for (;;) {
-        // consume staged rays into empty slots
-        const unsigned long long emask = __ballot(ray < 0);
-        const int take = min(__popcll(emask), s_count);
-        const int p = __popcll(emask & ((1ull << lane) - 1ull));
-        const bool fill = ray < 0 && p < take;
-        const int src = fill ? ((s_head + p) & 63) : lane;
-        const int n_ray = __shfl(s_ray, src), n_st = __shfl(s_st, src);
-        const float n_ox = __shfl(s_ox, src), n_oy = __shfl(s_oy, src), n_oz = __shfl(s_oz, src);
-        const float n_vx = __shfl(s_vx, src), n_vy = __shfl(s_vy, src), n_vz = __shfl(s_vz, src);
-        const float n_tt = __shfl(s_tt, src), n_tau = __shfl(s_tau, src);
-        if (fill) {
-          ray = n_ray;
-          st = n_st;
-          ox = n_ox;
-          oy = n_oy;
-          oz = n_oz;
-          vx = n_vx;
-          vy = n_vy;
-          vz = n_vz;
-          tt = n_tt;
-          tau = n_tau;
-          k = 0;
+  const bool paired = sm.simd_count[0] == 2 && sm.simd_count[1] == 2 && sm.simd_count[2] == 2 && sm.simd_count[3] == 2;
+  return __builtin_amdgcn_readfirstlane(paired ? sm.role_of[wave] : wave);
+}
+
+// Stage s of the evaluating roles.  Team 2's accumulators carry tile s-2's
+// product into stage s+1.
+template <int P, bool TAN, bool RED>
+__device__ inline void pipe_team1(PipeSmem& sm, const PipeWeights<P>& W, const DevLevel& L, f32x16_t (&acc)[2], int s,
+                                  int wave, const PipeLane& pl) {
+  const int tw = wave & 3;
+  if (sm.tlive[(s + 7) & 7]) {
+    pipe_hidden<P>(W, sm.act0[(s + 1) & 1], (TAN && pl.c) ? sm.zeros : sm.bias[0], acc, tw, pl);
+    pipe_store<P, TAN, RED>(acc, sm.act1[(s + 1) & 1], tw, pl);
+  }
+  if (sm.tlive[s & 7]) pipe_layer0<P, TAN>(W, sm.xin[s & 1], sm.act0[s & 1], L.d_in, wave, pl);
+}
+
+// Team 2 in two calls: the output sines (which free the accumulators; the
+// control step runs in between), then layer 0 and the second hidden product.
+template <bool TAN, bool RED>
+__device__ inline void pipe_team2_out(PipeSmem& sm, const f32x16_t (&acc)[2], int s, int wave, const PipeLane& pl) {
+  const int tw = wave & 3;
+  if (sm.tlive[(s + 5) & 7]) {
+    const float p = pipe_dot<TAN, RED>(acc, sm.wk, tw, pl);
+    if (pl.g == 0) sm.part[(s + 1) & 1][tw][pl.j] = p;
+  }
+}
+
+template <int P, bool TAN>
+__device__ inline void pipe_team2_in(PipeSmem& sm, const PipeWeights<P>& W, const DevLevel& L, f32x16_t (&acc)[2], int s,
+                                     int wave, const PipeLane& pl) {
+  const int tw = wave & 3;
+  if (sm.tlive[s & 7]) pipe_layer0<P, TAN>(W, sm.xin[s & 1], sm.act0[s & 1], L.d_in, wave, pl);
+  if (sm.tlive[(s + 6) & 7]) {
+    pipe_hidden<P>(W, sm.act1[s & 1], (TAN && pl.c) ? sm.zeros : sm.bias[1], acc, tw, pl);
+  } else {
+    // overwritten on both paths: the accumulators are dead between the two calls
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[rb][r] = 0.f;
+  }
+}
+
+// Stop flag and tile/group liveness, written by lane 0 of the control wave.
+__device__ inline void pipe_publish(PipeSmem& sm, int s, int G, bool live, bool more) {
+  sm.glive[G] = live ? 1 : 0;
+  sm.tlive[(s + 1) & 7] = live ? 1 : 0;
+  int any = live ? 1 : 0;
+#pragma unroll
+  for (int gg = 0; gg < kPipeGroups; ++gg)
+    if (gg != G) any |= sm.glive[gg];
+  sm.stop[(s + 2) & 1] = (!any && !more) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Tracing control (role 4): 32 ray slots per group, one per lane 0..31, and a
+// 64-entry staging ring of prefetched rays (lane e holds entry e) that refills
+// freed slots by lane shuffles and is topped up right after, so its loads
+// complete while the pipeline runs.
+struct TraceCtl {
+  int s_ray, s_st;
+  float s_ox, s_oy, s_oz, s_vx, s_vy, s_vz, s_tt, s_tau;
+  int s_head, s_count;
+  int cur, end, seg, seg_tries, chunk, seg_len, n_in;
+  bool exhausted;
+  int ring_start, ring_n;
+
+  __device__ inline void init(const TraceLevelArgs& A) {
+    n_in = A.in_count ? *A.in_count : A.n;
+    s_ray = -1;
+    s_st = 0;
+    s_ox = s_oy = s_oz = s_vx = s_vy = s_vz = s_tt = s_tau = 0.f;
+    s_head = s_count = 0;
+    cur = end = 0;
+    chunk = min(kChunk, max(64, (n_in / (8 * (int)gridDim.x)) & ~63));
+    seg_len = (n_in + kSegments - 1) / kSegments;
+    seg = blockIdx.x % kSegments;
+    seg_tries = 0;
+    exhausted = false;
+    ring_start = ring_n = 0;
+  }
+
+  // Fill the staging ring up to 64 entries from the segmented input queue.
+  __device__ inline void top_up(const TraceLevelArgs& A, int lane) {
+    while (s_count < 64 && !exhausted) {
+      if (cur >= end) {
+        const int s0 = seg * seg_len;
+        const int s_len = max(0, min(seg_len, n_in - s0));
+        int base = 0;
+        if (lane == 0) base = atomicAdd(A.in_heads + seg * kHeadStride, chunk);
+        base = __shfl(base, 0);
+        if (base >= s_len) {
+          seg = (seg + 1) % kSegments;
+          if (++seg_tries >= kSegments) exhausted = true;
+          continue;
         }
-        s_head = (s_head + take) & 63;
-        s_count -= take;
-        // top the staging ring up with new queue entries (loads issued, not awaited)
-        while (s_count < 64 && !exhausted) {
-          if (cur >= end) {
-            const int s0 = seg * seg_len;
-            const int s_len = max(0, min(seg_len, n_in - s0));
-            int base = 0;
-            if (lane == 0) base = atomicAdd(A.in_heads + seg * kHeadStride, chunk);
-            base = __shfl(base, 0);
-            if (base >= s_len) {
-              seg = (seg + 1) % kSegments;
-              if (++seg_tries >= kSegments) exhausted = true;
-              continue;
-            }
-            cur = s0 + base;
-            end = s0 + min(base + chunk, s_len);
-          }
-          const int add = min(64 - s_count, end - cur);
-          const int q = ((lane - s_head) & 63) - s_count;
-          if (q >= 0 && q < add) {
-            const int idx = cur + q;
-            s_ray = A.in_queue ? A.in_queue[idx] : idx;
-            s_ox = A.o[3 * s_ray + 0];
-            s_oy = A.o[3 * s_ray + 1];
-            s_oz = A.o[3 * s_ray + 2];
-            s_vx = A.v[3 * s_ray + 0];
-            s_vy = A.v[3 * s_ray + 1];
-            s_vz = A.v[3 * s_ray + 2];
-            s_tt = A.t ? A.t[s_ray] : 0.f;
-            if (A.level == 0) {
-              s_tau = 0.f;
-              s_st = 0;
-              if (A.steps)
-                for (int jj = 1; jj < A.m; ++jj) A.steps[(long long)s_ray * A.m + jj] = 0;
-            } else {
-              s_tau = A.depth[s_ray];
-              s_st = A.status[s_ray];
-            }
-          }
-          s_count += add;
-          cur += add;
-        }
-        live = __ballot(ray >= 0) != 0ull;
-        // an empty tile while rays are still staged: consume again
-        if (live || s_count == 0) break;
+        cur = s0 + base;
+        end = s0 + min(base + chunk, s_len);
       }
-      x = fmaf(tau, vx, ox);
-      y = fmaf(tau, vy, oy);
-      z = fmaf(tau, vz, oz);
-      center_at(A.B, tt, cx, cy);
-      sm.xin[lane] = net_input(L, x, y, z, tt, cx, cy);
-      if (lane == 0) sm.flag = live ? 1 : 0;
-    }
-    __syncthreads();
-    if (sm.flag == 0) break;
-    float part[2];
-    ws_eval<P, false>(sm, W, L, part);
-    if (g == 0) {
-      sm.part[wave][lane] = part[0];
-      sm.part[wave][32 + lane] = part[1];
-    }
-    __syncthreads();
-    if (wave == 0) {
-      const float N = sm.part[0][lane] + sm.part[1][lane] + sm.part[2][lane] + sm.part[3][lane] + L.bk;
-      int outcome = 0;
-      if (ray >= 0) {
-        float base_term = 0.f;
-        if (A.B.sphere) {
-          const float dx = x - cx, dy = y - cy;
-          base_term = sqrtf(fmaf(dx, dx, fmaf(dy, dy, z * z))) - A.B.r0;
-        }
-        const float f = fmaf(L.amplitude, N, base_term);
-        const float d = f - A.delta;
-        ++k;
-        if (!isfinite(d)) {
-          st |= ST_NONFINITE;
-          outcome = 2;
+      const int add = min(64 - s_count, end - cur);
+      const int q = ((lane - s_head) & 63) - s_count;
+      if (q >= 0 && q < add) {
+        const int idx = cur + q;
+        s_ray = A.in_queue ? A.in_queue[idx] : idx;
+        s_ox = A.o[3 * s_ray + 0];
+        s_oy = A.o[3 * s_ray + 1];
+        s_oz = A.o[3 * s_ray + 2];
+        s_vx = A.v[3 * s_ray + 0];
+        s_vy = A.v[3 * s_ray + 1];
+        s_vz = A.v[3 * s_ray + 2];
+        s_tt = A.t ? A.t[s_ray] : 0.f;
+        if (A.level == 0) {
+          s_tau = 0.f;
+          s_st = 0;
+          if (A.steps)
+            for (int jj = 1; jj < A.m; ++jj) A.steps[(long long)s_ray * A.m + jj] = 0;
         } else {
-          if (d < 0.f) st |= ST_NEG_STEP;
-          tau = fmaf(A.step_scale, d, tau);
-          if (tau > A.far) {
-            st |= ST_FAR;
-            outcome = 2;
-          } else if (d <= A.eps) {
-            outcome = 1;
-          } else if (k >= A.max_steps) {
-            st |= ST_BUDGET;
-            outcome = 2;
-          }
+          s_tau = A.depth[s_ray];
+          s_st = A.status[s_ray];
         }
       }
-      const unsigned long long pmask = __ballot(outcome == 1);
-      if (pmask && A.out_queue) {
-        if (outcome == 1) sm.ring[(ring_start + ring_n + __popcll(pmask & ((1ull << lane) - 1ull))) & (2 * kPushBatch - 1)] = ray;
-        ring_n += __popcll(pmask);
-        if (ring_n >= kPushBatch) {
-          __builtin_amdgcn_wave_barrier();
-          int base = 0;
-          if (lane == 0) base = atomicAdd(A.out_count, kPushBatch);
-          base = __shfl(base, 0);
-          A.out_queue[base + lane] = sm.ring[(ring_start + lane) & (2 * kPushBatch - 1)];
-          __builtin_amdgcn_wave_barrier();
-          ring_start = (ring_start + kPushBatch) & (2 * kPushBatch - 1);
-          ring_n -= kPushBatch;
-        }
-      }
-      if (outcome != 0) {
-        if (A.steps) A.steps[(long long)ray * A.m + A.level] = (uint8_t)k;
-        if (outcome == 2) {
-          A.depth[ray] = __builtin_inff();
-          A.hit[ray] = 0;
-          A.status[ray] = (uint8_t)st;
-          if (A.normal) {
-            A.normal[3 * ray + 0] = 0.f;
-            A.normal[3 * ray + 1] = 0.f;
-            A.normal[3 * ray + 2] = 0.f;
-          }
-        } else if (A.is_final) {
-          A.depth[ray] = tau;
-          A.hit[ray] = 1;
-          A.status[ray] = (uint8_t)(st | ST_HIT);
-        } else {
-          A.depth[ray] = tau;
-          A.status[ray] = (uint8_t)st;
-        }
-        ray = -1;
-      }
+      s_count += add;
+      cur += add;
     }
   }
-  if (wave == 0 && ring_n > 0 && A.out_queue) {
+
+  __device__ inline void push(PipeSmem& sm, const TraceLevelArgs& A, int lane, bool hit, int ray) {
+    const unsigned long long pmask = __ballot(hit);
+    if (!pmask || !A.out_queue) return;
+    if (hit) sm.ring[(ring_start + ring_n + __popcll(pmask & ((1ull << lane) - 1ull))) & (2 * kPushBatch - 1)] = ray;
+    ring_n += __popcll(pmask);
+    if (ring_n >= kPushBatch) {
+      __builtin_amdgcn_wave_barrier();
+      int base = 0;
+      if (lane == 0) base = atomicAdd(A.out_count, kPushBatch);
+      base = __shfl(base, 0);
+      A.out_queue[base + lane] = sm.ring[(ring_start + lane) & (2 * kPushBatch - 1)];
+      __builtin_amdgcn_wave_barrier();
+      ring_start = (ring_start + kPushBatch) & (2 * kPushBatch - 1);
+      ring_n -= kPushBatch;
+    }
+  }
+
+  __device__ inline void flush(PipeSmem& sm, const TraceLevelArgs& A, int lane) {
+    if (ring_n == 0 || !A.out_queue) return;
     __builtin_amdgcn_wave_barrier();
     int base = 0;
     if (lane == 0) base = atomicAdd(A.out_count, ring_n);
     base = __shfl(base, 0);
     if (lane < ring_n) A.out_queue[base + lane] = sm.ring[(ring_start + lane) & (2 * kPushBatch - 1)];
   }
-}
 
-template <int P>
-__global__ void __launch_bounds__(kBlockThreads, 1) k_normal_ws(NormalArgs A) {
-  __shared__ WsSmem sm;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 5;
-  const DevLevel& L = A.L;
-  WsWeights<P> W;
-  W.load(L, wave, lane);
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) {
-    sm.bias[0][i] = L.bh_plain[i];
-    sm.bias[1][i] = L.bh_plain[256 + i];
-    sm.wk[i] = L.wk_plain[i];
+  // Stage s (s = -1: prologue): finish tile s-4, refill its group, write tile s+1.
+  __device__ inline void step(PipeSmem& sm, const TraceLevelArgs& A, int s, int lane) {
+    const DevLevel& L = A.L;
+    const int G = (s + 1) % kPipeGroups;
+    const bool slot = lane < kPipeCols;
+    const int sl = lane & (kPipeCols - 1);
+    int ray = -1, k = 0, st = 0;
+    float tau = 0.f, ox = 0.f, oy = 0.f, oz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, tt = 0.f;
+    if (slot) {
+      ray = sm.sray[G][sl];
+      k = sm.sk[G][sl];
+      st = sm.sst[G][sl];
+      tau = sm.sf[0][G][sl];
+      ox = sm.sf[1][G][sl];
+      oy = sm.sf[2][G][sl];
+      oz = sm.sf[3][G][sl];
+      vx = sm.sf[4][G][sl];
+      vy = sm.sf[5][G][sl];
+      vz = sm.sf[6][G][sl];
+      tt = sm.sf[7][G][sl];
+    }
+    // Algorithm 1 update with the outputs of tile s-4 (part[(s - 4) % 2])
+    int outcome = 0;
+    if (ray >= 0) {
+      const int pb = s & 1;
+      const float N = sm.part[pb][0][sl] + sm.part[pb][1][sl] + sm.part[pb][2][sl] + sm.part[pb][3][sl] + L.bk;
+      float base_term = 0.f;
+      if (A.B.sphere) {
+        float cx, cy;
+        center_at(A.B, tt, cx, cy);
+        const float x = fmaf(tau, vx, ox), y = fmaf(tau, vy, oy), z = fmaf(tau, vz, oz);
+        const float dx = x - cx, dy = y - cy;
+        base_term = sqrtf(fmaf(dx, dx, fmaf(dy, dy, z * z))) - A.B.r0;
+      }
+      const float f = fmaf(L.amplitude, N, base_term);
+      const float d = f - A.delta;
+      ++k;
+      if (!isfinite(d)) {
+        st |= ST_NONFINITE;
+        outcome = 2;
+      } else {
+        if (d < 0.f) st |= ST_NEG_STEP;
+        tau = fmaf(A.step_scale, d, tau);
+        if (tau > A.far) {
+          st |= ST_FAR;
+          outcome = 2;
+        } else if (d <= A.eps) {
+          outcome = 1;
+        } else if (k >= A.max_steps) {
+          st |= ST_BUDGET;
+          outcome = 2;
+        }
+      }
+    }
+    push(sm, A, lane, outcome == 1, ray);
+    if (outcome != 0) {
+      if (A.steps) A.steps[(long long)ray * A.m + A.level] = (uint8_t)k;
+      if (outcome == 2) {
+        A.depth[ray] = __builtin_inff();
+        A.hit[ray] = 0;
+        A.status[ray] = (uint8_t)st;
+        if (A.normal) {
+          A.normal[3 * ray + 0] = 0.f;
+          A.normal[3 * ray + 1] = 0.f;
+          A.normal[3 * ray + 2] = 0.f;
+        }
+      } else if (A.is_final) {
+        A.depth[ray] = tau;
+        A.hit[ray] = 1;
+        A.status[ray] = (uint8_t)(st | ST_HIT);
+      } else {
+        A.depth[ray] = tau;
+        A.status[ray] = (uint8_t)st;
+      }
+      ray = -1;
+    }
+    // refill freed slots from the staging ring, then top the ring up
+    const unsigned long long emask = __ballot(slot && ray < 0);
+    const int take = min(__popcll(emask), s_count);
+    const int p = __popcll(emask & ((1ull << lane) - 1ull));
+    const bool fill = slot && ray < 0 && p < take;
+    const int src = fill ? ((s_head + p) & 63) : lane;
+    const int n_ray = __shfl(s_ray, src), n_st = __shfl(s_st, src);
+    const float n_ox = __shfl(s_ox, src), n_oy = __shfl(s_oy, src), n_oz = __shfl(s_oz, src);
+    const float n_vx = __shfl(s_vx, src), n_vy = __shfl(s_vy, src), n_vz = __shfl(s_vz, src);
+    const float n_tt = __shfl(s_tt, src), n_tau = __shfl(s_tau, src);
+    if (fill) {
+      ray = n_ray;
+      st = n_st;
+      ox = n_ox;
+      oy = n_oy;
+      oz = n_oz;
+      vx = n_vx;
+      vy = n_vy;
+      vz = n_vz;
+      tt = n_tt;
+      tau = n_tau;
+      k = 0;
+    }
+    s_head = (s_head + take) & 63;
+    s_count -= take;
+    top_up(A, lane);
+    // inputs of tile s+1
+    const bool live = __ballot(slot && ray >= 0) != 0ull;
+    if (slot) {
+      sm.sray[G][sl] = ray;
+      sm.sk[G][sl] = k;
+      sm.sst[G][sl] = st;
+      sm.sf[0][G][sl] = tau;
+      sm.sf[1][G][sl] = ox;
+      sm.sf[2][G][sl] = oy;
+      sm.sf[3][G][sl] = oz;
+      sm.sf[4][G][sl] = vx;
+      sm.sf[5][G][sl] = vy;
+      sm.sf[6][G][sl] = vz;
+      sm.sf[7][G][sl] = tt;
+      float cx, cy;
+      center_at(A.B, tt, cx, cy);
+      sm.xin[(s + 1) & 1][sl] = net_input(L, fmaf(tau, vx, ox), fmaf(tau, vy, oy), fmaf(tau, vz, oz), tt, cx, cy);
+    }
+    if (lane == 0) pipe_publish(sm, s, G, live, s_count > 0 || !exhausted);
+  }
+};
+
+// One team's side of the tracing kernel; TEAM2's role 4 runs the control.  The
+// two sides execute the same number of workgroup barriers.
+template <int P, bool RED, bool TEAM2>
+__device__ inline void trace_body(PipeSmem& sm, const TraceLevelArgs& A, int wave, int lane) {
+  PipeWeights<P> W;
+  W.load(A.L, wave, lane);
+  const PipeLane pl = pipe_lane<false>(lane);
+  const bool ctl_wave = TEAM2 && wave == 4;
+  TraceCtl ctl;
+  if (ctl_wave) {
+    ctl.init(A);
+    ctl.top_up(A, lane);
   }
   __syncthreads();
-  const int n_in = A.count ? *A.count : A.n;
-  const int q = lane >> 2, c = lane & 3;  // wave 0: lane = column, 16 points x 4 columns
-  for (int base = blockIdx.x * 16; base < n_in; base += gridDim.x * 16) {
-    int ray = -1;
-    float x = 0.f, y = 0.f, z = 0.f, tt = 0.f, cx = 0.f, cy = 0.f;
-    if (wave == 0) {
-      const int slot = base + q;
-      ray = (slot < n_in) ? (A.queue ? A.queue[slot] : slot) : -1;
-      if (ray >= 0) {
-        const float tau = A.depth[ray];
-        x = fmaf(tau, A.v[3 * ray + 0], A.o[3 * ray + 0]);
-        y = fmaf(tau, A.v[3 * ray + 1], A.o[3 * ray + 1]);
-        z = fmaf(tau, A.v[3 * ray + 2], A.o[3 * ray + 2]);
-        tt = A.t ? A.t[ray] : 0.f;
-      }
-      center_at(A.B, tt, cx, cy);
-      sm.xin[lane] = net_input(L, x, y, z, tt, cx, cy);
+  if (ctl_wave) ctl.step(sm, A, -1, lane);
+  __syncthreads();
+  f32x16_t acc[2];
+  for (int s = 0;; ++s) {
+    if (sm.stop[(s + 1) & 1]) break;
+    if (!TEAM2) {
+      pipe_team1<P, false, RED>(sm, W, A.L, acc, s, wave, pl);
+    } else {
+      pipe_team2_out<false, RED>(sm, acc, s, wave, pl);
+      if (ctl_wave) ctl.step(sm, A, s, lane);
+      pipe_team2_in<P, false>(sm, W, A.L, acc, s, wave, pl);
     }
     __syncthreads();
-    float part[2];
-    ws_eval<P, true>(sm, W, L, part);
-    if (g == 0) {
-      sm.part[wave][lane] = part[0];
-      sm.part[wave][32 + lane] = part[1];
+  }
+  if (ctl_wave) ctl.flush(sm, A, lane);
+}
+
+template <int P, bool RED>
+__global__ void __launch_bounds__(kPipeThreads, 1) k_trace_ws(TraceLevelArgs A) {
+  __shared__ PipeSmem sm;
+  pipe_setup(sm, A.L);
+  __syncthreads();
+  const int wave = pipe_role(sm);
+  if (wave < 4)
+    trace_body<P, RED, false>(sm, A, wave, threadIdx.x & 63);
+  else
+    trace_body<P, RED, true>(sm, A, wave, threadIdx.x & 63);
+}
+
+// ---------------------------------------------------------------------------
+// Normal control (role 4): 8 points per group (columns 4 q + c), fetched ahead:
+// in stage s the ray data of tile s+2 and the queue entries of tile s+3 are
+// loaded, so no stage waits on memory.
+struct NormalCtl {
+  int n_in, next;  // next: first queue slot of the next tile this workgroup fetches
+  int q_ray;       // lanes 0..7: queue entries two tiles ahead
+  int p_ray;       // lanes 0..7: rays of the next tile, with their data
+  float p_ox, p_oy, p_oz, p_vx, p_vy, p_vz, p_tau, p_t;
+
+  __device__ inline int fetch_id(const NormalArgs& A, int lane) {
+    const int slot = next + lane;
+    const int r = (lane < 8 && slot < n_in) ? (A.queue ? A.queue[slot] : slot) : -1;
+    next += 8 * gridDim.x;
+    return r;
+  }
+  __device__ inline void fetch_data(const NormalArgs& A) {
+    if (p_ray >= 0) {
+      p_ox = A.o[3 * p_ray + 0];
+      p_oy = A.o[3 * p_ray + 1];
+      p_oz = A.o[3 * p_ray + 2];
+      p_vx = A.v[3 * p_ray + 0];
+      p_vy = A.v[3 * p_ray + 1];
+      p_vz = A.v[3 * p_ray + 2];
+      p_tau = A.depth[p_ray];
+      p_t = A.t ? A.t[p_ray] : 0.f;
     }
-    __syncthreads();
-    if (wave == 0) {
-      float val = sm.part[0][lane] + sm.part[1][lane] + sm.part[2][lane] + sm.part[3][lane];
+  }
+  __device__ inline void init(const NormalArgs& A, int lane) {
+    n_in = A.count ? *A.count : A.n;
+    next = blockIdx.x * 8;
+    p_ox = p_oy = p_oz = p_vx = p_vy = p_vz = p_tau = p_t = 0.f;
+    p_ray = fetch_id(A, lane);
+    fetch_data(A);
+    q_ray = fetch_id(A, lane);
+  }
+
+  __device__ inline void step(PipeSmem& sm, const NormalArgs& A, int s, int lane) {
+    const DevLevel& L = A.L;
+    const int G = (s + 1) % kPipeGroups;
+    const bool col = lane < kPipeCols;
+    const int q = (lane >> 2) & 7, c = lane & 3;
+    // normals of tile s-4
+    if (sm.glive[G]) {
+      const int pb = s & 1;
+      const int sl = lane & (kPipeCols - 1);
+      float val = sm.part[pb][0][sl] + sm.part[pb][1][sl] + sm.part[pb][2][sl] + sm.part[pb][3][sl];
       if (c == 0) val += L.bk;
       const float gx = quad_bcast<1>(val), gy = quad_bcast<2>(val), gz = quad_bcast<3>(val);
-      if (c == 0 && ray >= 0) {
+      const int ray = sm.sray[G][q];
+      if (col && c == 0 && ray >= 0) {
+        const float x = sm.sf[0][G][q], y = sm.sf[1][G][q], z = sm.sf[2][G][q];
+        const float cx = sm.sf[3][G][q], cy = sm.sf[4][G][q];
         float fx = L.amplitude * gx, fy = L.amplitude * gy, fz = L.amplitude * gz;
         if (A.B.sphere) {
           const float dx = x - cx, dy = y - cy;
@@ -442,34 +626,109 @@ __global__ void __launch_bounds__(kBlockThreads, 1) k_normal_ws(NormalArgs A) {
         A.normal[3 * ray + 2] = fz * inv;
       }
     }
+    // tile s+1 from the prefetched points (lanes 0..7)
+    float x = 0.f, y = 0.f, z = 0.f, cx = 0.f, cy = 0.f;
+    if (p_ray >= 0) {
+      x = fmaf(p_tau, p_vx, p_ox);
+      y = fmaf(p_tau, p_vy, p_oy);
+      z = fmaf(p_tau, p_vz, p_oz);
+      center_at(A.B, p_t, cx, cy);
+    }
+    const bool live = __ballot(p_ray >= 0) != 0ull;
+    if (lane < 8) {
+      sm.sray[G][lane] = p_ray;
+      sm.sf[0][G][lane] = x;
+      sm.sf[1][G][lane] = y;
+      sm.sf[2][G][lane] = z;
+      sm.sf[3][G][lane] = cx;
+      sm.sf[4][G][lane] = cy;
+    }
+    const float qx = __shfl(x, q), qy = __shfl(y, q), qz = __shfl(z, q), qt = __shfl(p_t, q);
+    const float qcx = __shfl(cx, q), qcy = __shfl(cy, q);
+    if (col) sm.xin[(s + 1) & 1][lane] = net_input(L, qx, qy, qz, qt, qcx, qcy);
+    // prefetch: data of tile s+2, queue entries of tile s+3
+    p_ray = q_ray;
+    fetch_data(A);
+    q_ray = fetch_id(A, lane);
+    // later tiles hold points only if tile s+2 does (tiles are fetched in slot order)
+    const bool more = __ballot(p_ray >= 0) != 0ull;
+    if (lane == 0) pipe_publish(sm, s, G, live, more);
+  }
+};
+
+template <int P, bool RED, bool TEAM2>
+__device__ inline void normal_body(PipeSmem& sm, const NormalArgs& A, int wave, int lane) {
+  PipeWeights<P> W;
+  W.load(A.L, wave, lane);
+  const PipeLane pl = pipe_lane<true>(lane);
+  const bool ctl_wave = TEAM2 && wave == 4;
+  NormalCtl ctl;
+  if (ctl_wave) ctl.init(A, lane);
+  __syncthreads();
+  if (ctl_wave) ctl.step(sm, A, -1, lane);
+  __syncthreads();
+  f32x16_t acc[2];
+  for (int s = 0;; ++s) {
+    if (sm.stop[(s + 1) & 1]) break;
+    if (!TEAM2) {
+      pipe_team1<P, true, RED>(sm, W, A.L, acc, s, wave, pl);
+    } else {
+      pipe_team2_out<true, RED>(sm, acc, s, wave, pl);
+      if (ctl_wave) ctl.step(sm, A, s, lane);
+      pipe_team2_in<P, true>(sm, W, A.L, acc, s, wave, pl);
+    }
+    __syncthreads();
   }
 }
 
-hipError_t launch_trace_ws(int prec, const TraceLevelArgs& a, int grid, hipStream_t s) {
+template <int P, bool RED>
+__global__ void __launch_bounds__(kPipeThreads, 1) k_normal_ws(NormalArgs A) {
+  __shared__ PipeSmem sm;
+  pipe_setup(sm, A.L);
+  __syncthreads();
+  const int wave = pipe_role(sm);
+  if (wave < 4)
+    normal_body<P, RED, false>(sm, A, wave, threadIdx.x & 63);
+  else
+    normal_body<P, RED, true>(sm, A, wave, threadIdx.x & 63);
+}
+
+template <bool RED>
+static hipError_t launch_trace_ws_r(int prec, const TraceLevelArgs& a, int grid, hipStream_t s) {
   if (prec == PREC_BF16)
-    hipLaunchKernelGGL(k_trace_ws<PREC_BF16>, dim3(grid), dim3(kBlockThreads), 0, s, a);
+    hipLaunchKernelGGL((k_trace_ws<PREC_BF16, RED>), dim3(grid), dim3(kPipeThreads), 0, s, a);
   else if (prec == PREC_FP16)
-    hipLaunchKernelGGL(k_trace_ws<PREC_FP16>, dim3(grid), dim3(kBlockThreads), 0, s, a);
+    hipLaunchKernelGGL((k_trace_ws<PREC_FP16, RED>), dim3(grid), dim3(kPipeThreads), 0, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+template <bool RED>
+static hipError_t launch_normal_ws_r(int prec, const NormalArgs& a, int grid, hipStream_t s) {
+  if (prec == PREC_BF16)
+    hipLaunchKernelGGL((k_normal_ws<PREC_BF16, RED>), dim3(grid), dim3(kPipeThreads), 0, s, a);
+  else if (prec == PREC_FP16)
+    hipLaunchKernelGGL((k_normal_ws<PREC_FP16, RED>), dim3(grid), dim3(kPipeThreads), 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_ws(int prec, const TraceLevelArgs& a, int grid, hipStream_t s) {
+  return a.L.reduce_hidden ? launch_trace_ws_r<true>(prec, a, grid, s) : launch_trace_ws_r<false>(prec, a, grid, s);
 }
 
 hipError_t launch_normal_ws(int prec, const NormalArgs& a, int grid, hipStream_t s) {
-  if (prec == PREC_BF16)
-    hipLaunchKernelGGL(k_normal_ws<PREC_BF16>, dim3(grid), dim3(kBlockThreads), 0, s, a);
-  else if (prec == PREC_FP16)
-    hipLaunchKernelGGL(k_normal_ws<PREC_FP16>, dim3(grid), dim3(kBlockThreads), 0, s, a);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  return a.L.reduce_hidden ? launch_normal_ws_r<true>(prec, a, grid, s) : launch_normal_ws_r<false>(prec, a, grid, s);
 }
 
 int ws_resident_blocks(int prec, int kind, int device) {
-  const void* fn = prec == PREC_FP16 ? (kind == 0 ? (const void*)k_trace_ws<PREC_FP16> : (const void*)k_normal_ws<PREC_FP16>)
-                                     : (kind == 0 ? (const void*)k_trace_ws<PREC_BF16> : (const void*)k_normal_ws<PREC_BF16>);
+  const void* fn = prec == PREC_FP16
+                       ? (kind == 0 ? (const void*)k_trace_ws<PREC_FP16, false> : (const void*)k_normal_ws<PREC_FP16, false>)
+                       : (kind == 0 ? (const void*)k_trace_ws<PREC_BF16, false> : (const void*)k_normal_ws<PREC_BF16, false>);
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlockThreads, 0) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPipeThreads, 0) != hipSuccess || per_cu < 1)
     per_cu = 1;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
