@@ -17,11 +17,11 @@
 //     the 16-bit activations to act1[(s-1) % 2]: MFMA first, then VALU;
 //   * team 2 applies sin to its accumulators of tile s-3 and forms its part of
 //     the output dot product, then multiplies tile s-2 (act1) by its rows of
-//     W_2: VALU first, then MFMA (its first wave runs the control step between
-//     the two, while its accumulators are free);
-//   * one team-2 wave takes the outputs of tile s-4, runs the Algorithm 1 update (or
-//     the normal's last step), retires finished rays, refills the freed slots
-//     and writes the inputs of tile s+1.
+//     W_2: VALU first, then MFMA;
+//   * role 0 (a team-1 wave, after its sines; when tracing, role 1 takes over
+//     its first-layer block) takes the outputs of tile s-4, runs the
+//     Algorithm 1 update (or the normal's last step), retires finished rays,
+//     refills the freed slots and writes the inputs of tile s+1.
 // The two teams' MFMA and VALU phases are opposite, so each SIMD overlaps one
 // wave's matrix work with the other's sines.  Tile t occupies slot group
 // t % kPipeGroups; the ray state of a group waits in LDS while its tile is in
@@ -35,6 +35,7 @@ namespace nnm {
 constexpr int kPipeThreads = 512;
 constexpr int kPipeCols = 32;         // columns per tile
 constexpr int kPipeStride = 256 + 8;  // 16-bit elements per LDS column (spreads LDS banks)
+constexpr int kParkMax = 16;          // most survivors a group parks (tail compaction)
 static_assert(kPipeGroups == 5, "tile t uses group t % 5: five tiles are in flight");
 static_assert(kPipeGroups * kPipeCols == kWsRaysPerBlock && kPipeGroups * 8 == kWsPointsPerBlock, "slots");
 
@@ -46,12 +47,11 @@ struct PipeSmem {
   float wk[256];
   float part[2][4][kPipeCols];
   float4 xin[2][kPipeCols];
-  int sray[kPipeGroups][kPipeCols];
-  int sk[kPipeGroups][kPipeCols];
-  int sst[kPipeGroups][kPipeCols];
-  float sf[8][kPipeGroups][kPipeCols];
+  // slot records, three float4 per slot: tracing {o, tau} {v, t} {ray, k | st << 16, c(t)};
+  // normal {x, 0} {c(t), 0, 0} {ray, 0, 0, 0}
+  float4 srec[kPipeGroups][3][kPipeCols];
+  float4 park[3][kPipeCols];  // tracing: parked slot records (tail compaction)
   int tlive[8];
-  int glive[kPipeGroups];
   int stop[2];
   int simd_count[4];
   int role_of[8];
@@ -105,13 +105,16 @@ __device__ inline float pipe_act(float v, const PipeLane& pl) {
 template <int P>
 struct PipeWeights {
   typedef typename HiddenOps<P>::frag_t frag_t;
-  float w0[3];
+  float w0[2][3];  // layer-0 row blocks: its own, and (role 1 when role 0 hands it over) block 0
   frag_t w[2][16];
 
   __device__ inline void load(const DevLevel& L, int wave, int lane) {
     const int team = wave >> 2, tw = wave & 3;
 #pragma unroll
-    for (int ks = 0; ks < 3; ++ks) w0[ks] = L.ws_a0[(wave * 3 + ks) * 64 + lane];
+    for (int ks = 0; ks < 3; ++ks) {
+      w0[0][ks] = L.ws_a0[(wave * 3 + ks) * 64 + lane];
+      w0[1][ks] = wave == 1 ? L.ws_a0[ks * 64 + lane] : 0.f;
+    }
     const frag_t* WA = (const frag_t*)L.ws_ah;
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
@@ -130,9 +133,9 @@ __device__ inline void pipe_store4(uint16_t* dst, uint16_t h0, uint16_t h1, uint
   *(uint2*)dst = packed;
 }
 
-// First sine layer, rows [32 wave, 32 wave + 32) of one tile.
+// First sine layer, rows [32 blk, 32 blk + 32) of one tile (operand W.w0[slot]).
 template <int P, bool TAN>
-__device__ inline void pipe_layer0(const PipeWeights<P>& W, const float4* xin, uint16_t* dst, int d_in, int wave,
+__device__ inline void pipe_layer0(const PipeWeights<P>& W, int slot, const float4* xin, uint16_t* dst, int d_in, int blk,
                                    const PipeLane& pl) {
   const float4 in = xin[pl.j];
   const int ks0 = d_in == 4 ? 3 : 2;
@@ -142,13 +145,13 @@ __device__ inline void pipe_layer0(const PipeWeights<P>& W, const float4* xin, u
 #pragma unroll
   for (int ks = 0; ks < 3; ++ks)
     if (ks < ks0)
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(W.w0[ks], layer0_input(in, d_in, pl.c, ks, pl.g), acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(W.w0[slot][ks], layer0_input(in, d_in, pl.c, ks, pl.g), acc, 0, 0, 0);
 #pragma unroll
   for (int b4 = 0; b4 < 4; ++b4) {
     uint16_t h[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) h[i] = PipeBits<P>::bits(pipe_act<TAN, true>(acc[4 * b4 + i], pl));
-    pipe_store4(&dst[pl.j * kPipeStride + 32 * wave + 8 * b4 + 4 * pl.g], h[0], h[1], h[2], h[3]);
+    pipe_store4(&dst[pl.j * kPipeStride + 32 * blk + 8 * b4 + 4 * pl.g], h[0], h[1], h[2], h[3]);
   }
 }
 
@@ -215,9 +218,9 @@ __device__ inline void pipe_setup(PipeSmem& sm, const DevLevel& L) {
     sm.wk[i] = L.wk_plain[i];
     sm.zeros[i] = 0.f;
   }
-  for (int i = threadIdx.x; i < kPipeGroups * kPipeCols; i += kPipeThreads) (&sm.sray[0][0])[i] = -1;
+  for (int i = threadIdx.x; i < kPipeGroups * kPipeCols; i += kPipeThreads)
+    sm.srec[i / kPipeCols][2][i % kPipeCols] = make_float4(__int_as_float(-1), 0.f, 0.f, 0.f);
   if (threadIdx.x < 8) sm.tlive[threadIdx.x] = 0;
-  if (threadIdx.x < kPipeGroups) sm.glive[threadIdx.x] = 0;
   if (threadIdx.x < 2) sm.stop[threadIdx.x] = 0;
   if (threadIdx.x < 4) sm.simd_count[threadIdx.x] = 0;
 }
@@ -240,21 +243,29 @@ __device__ inline int pipe_role(PipeSmem& sm) {
   return __builtin_amdgcn_readfirstlane(paired ? sm.role_of[wave] : wave);
 }
 
-// Stage s of the evaluating roles.  Team 2's accumulators carry tile s-2's
-// product into stage s+1.
+// Stage s of the evaluating roles.  Team 1: the first hidden product of tile
+// s-1 and its sines, then its block of the first layer of tile s (role 0 runs
+// the control in between).  Team 2 in two calls: the output sines of tile s-3,
+// then its first-layer block of tile s and the second hidden product of tile
+// s-2, whose accumulators carry into stage s+1.
 template <int P, bool TAN, bool RED>
-__device__ inline void pipe_team1(PipeSmem& sm, const PipeWeights<P>& W, const DevLevel& L, f32x16_t (&acc)[2], int s,
-                                  int wave, const PipeLane& pl) {
-  const int tw = wave & 3;
+__device__ inline void pipe_team1_hidden(PipeSmem& sm, const PipeWeights<P>& W, f32x16_t (&acc)[2], int s, int wave,
+                                         const PipeLane& pl) {
   if (sm.tlive[(s + 7) & 7]) {
-    pipe_hidden<P>(W, sm.act0[(s + 1) & 1], (TAN && pl.c) ? sm.zeros : sm.bias[0], acc, tw, pl);
-    pipe_store<P, TAN, RED>(acc, sm.act1[(s + 1) & 1], tw, pl);
+    pipe_hidden<P>(W, sm.act0[(s + 1) & 1], (TAN && pl.c) ? sm.zeros : sm.bias[0], acc, wave & 3, pl);
+    pipe_store<P, TAN, RED>(acc, sm.act1[(s + 1) & 1], wave & 3, pl);
   }
-  if (sm.tlive[s & 7]) pipe_layer0<P, TAN>(W, sm.xin[s & 1], sm.act0[s & 1], L.d_in, wave, pl);
 }
 
-// Team 2 in two calls: the output sines (which free the accumulators; the
-// control step runs in between), then layer 0 and the second hidden product.
+// OFF0: role 0 (the control wave) hands its first-layer block to role 1.
+template <int P, bool TAN, bool OFF0>
+__device__ inline void pipe_team1_layer0(PipeSmem& sm, const PipeWeights<P>& W, const DevLevel& L, int s, int wave,
+                                         const PipeLane& pl) {
+  if (!sm.tlive[s & 7]) return;
+  if (!OFF0 || wave != 0) pipe_layer0<P, TAN>(W, 0, sm.xin[s & 1], sm.act0[s & 1], L.d_in, wave, pl);
+  if (OFF0 && wave == 1) pipe_layer0<P, TAN>(W, 1, sm.xin[s & 1], sm.act0[s & 1], L.d_in, 0, pl);
+}
+
 template <bool TAN, bool RED>
 __device__ inline void pipe_team2_out(PipeSmem& sm, const f32x16_t (&acc)[2], int s, int wave, const PipeLane& pl) {
   const int tw = wave & 3;
@@ -268,7 +279,7 @@ template <int P, bool TAN>
 __device__ inline void pipe_team2_in(PipeSmem& sm, const PipeWeights<P>& W, const DevLevel& L, f32x16_t (&acc)[2], int s,
                                      int wave, const PipeLane& pl) {
   const int tw = wave & 3;
-  if (sm.tlive[s & 7]) pipe_layer0<P, TAN>(W, sm.xin[s & 1], sm.act0[s & 1], L.d_in, wave, pl);
+  if (sm.tlive[s & 7]) pipe_layer0<P, TAN>(W, 0, sm.xin[s & 1], sm.act0[s & 1], L.d_in, wave, pl);
   if (sm.tlive[(s + 6) & 7]) {
     pipe_hidden<P>(W, sm.act1[s & 1], (TAN && pl.c) ? sm.zeros : sm.bias[1], acc, tw, pl);
   } else {
@@ -280,19 +291,15 @@ __device__ inline void pipe_team2_in(PipeSmem& sm, const PipeWeights<P>& W, cons
   }
 }
 
-// Stop flag and tile/group liveness, written by lane 0 of the control wave.
-__device__ inline void pipe_publish(PipeSmem& sm, int s, int G, bool live, bool more) {
-  sm.glive[G] = live ? 1 : 0;
+// Tile liveness and the stop flag, written by lane 0 of the control wave;
+// glive is the control wave's bitmask of groups holding rays.
+__device__ inline void pipe_publish(PipeSmem& sm, int s, int glive, bool live, bool more) {
   sm.tlive[(s + 1) & 7] = live ? 1 : 0;
-  int any = live ? 1 : 0;
-#pragma unroll
-  for (int gg = 0; gg < kPipeGroups; ++gg)
-    if (gg != G) any |= sm.glive[gg];
-  sm.stop[(s + 2) & 1] = (!any && !more) ? 1 : 0;
+  sm.stop[(s + 2) & 1] = (glive == 0 && !more) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
-// Tracing control (role 4): 32 ray slots per group, one per lane 0..31, and a
+// Tracing control (role 0): 32 ray slots per group, one per lane 0..31, and a
 // 64-entry staging ring of prefetched rays (lane e holds entry e) that refills
 // freed slots by lane shuffles and is topped up right after, so its loads
 // complete while the pipeline runs.
@@ -303,8 +310,12 @@ struct TraceCtl {
   int cur, end, seg, seg_tries, chunk, seg_len, n_in;
   bool exhausted;
   int ring_start, ring_n;
+  int glive;  // bit G: slot group G holds rays
+  int park_head, park_count;
 
   __device__ inline void init(const TraceLevelArgs& A) {
+    glive = 0;
+    park_head = park_count = 0;
     n_in = A.in_count ? *A.in_count : A.n;
     s_ray = -1;
     s_st = 0;
@@ -396,19 +407,22 @@ struct TraceCtl {
     const bool slot = lane < kPipeCols;
     const int sl = lane & (kPipeCols - 1);
     int ray = -1, k = 0, st = 0;
-    float tau = 0.f, ox = 0.f, oy = 0.f, oz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, tt = 0.f;
+    float tau = 0.f, ox = 0.f, oy = 0.f, oz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, tt = 0.f, cx = 0.f, cy = 0.f;
     if (slot) {
-      ray = sm.sray[G][sl];
-      k = sm.sk[G][sl];
-      st = sm.sst[G][sl];
-      tau = sm.sf[0][G][sl];
-      ox = sm.sf[1][G][sl];
-      oy = sm.sf[2][G][sl];
-      oz = sm.sf[3][G][sl];
-      vx = sm.sf[4][G][sl];
-      vy = sm.sf[5][G][sl];
-      vz = sm.sf[6][G][sl];
-      tt = sm.sf[7][G][sl];
+      const float4 r0 = sm.srec[G][0][sl], r1 = sm.srec[G][1][sl], r2 = sm.srec[G][2][sl];
+      ox = r0.x;
+      oy = r0.y;
+      oz = r0.z;
+      tau = r0.w;
+      vx = r1.x;
+      vy = r1.y;
+      vz = r1.z;
+      tt = r1.w;
+      ray = __float_as_int(r2.x);
+      k = __float_as_int(r2.y) & 0xFFFF;
+      st = __float_as_int(r2.y) >> 16;
+      cx = r2.z;
+      cy = r2.w;
     }
     // Algorithm 1 update with the outputs of tile s-4 (part[(s - 4) % 2])
     int outcome = 0;
@@ -417,8 +431,6 @@ struct TraceCtl {
       const float N = sm.part[pb][0][sl] + sm.part[pb][1][sl] + sm.part[pb][2][sl] + sm.part[pb][3][sl] + L.bk;
       float base_term = 0.f;
       if (A.B.sphere) {
-        float cx, cy;
-        center_at(A.B, tt, cx, cy);
         const float x = fmaf(tau, vx, ox), y = fmaf(tau, vy, oy), z = fmaf(tau, vz, oz);
         const float dx = x - cx, dy = y - cy;
         base_term = sqrtf(fmaf(dx, dx, fmaf(dy, dy, z * z))) - A.B.r0;
@@ -465,7 +477,51 @@ struct TraceCtl {
       }
       ray = -1;
     }
-    // refill freed slots from the staging ring, then top the ring up
+    // Tail compaction.  Once the queue is drained, a group with few survivors
+    // parks them in LDS and its next tile is dark (a cheap stage); the next
+    // group with free slots takes them in.  Live rays so gather in fewer tiles
+    // while the last, longest rays finish.
+    bool parked = false;
+    if (exhausted && s_count == 0 && park_count == 0) {
+      const unsigned long long smask = __ballot(slot && ray >= 0);
+      const int nsurv = __popcll(smask);
+      if (nsurv > 0 && nsurv <= kParkMax) {
+        if (slot && ray >= 0) {
+          const int e = (park_head + __popcll(smask & ((1ull << lane) - 1ull))) & (kPipeCols - 1);
+          sm.park[0][e] = make_float4(ox, oy, oz, tau);
+          sm.park[1][e] = make_float4(vx, vy, vz, tt);
+          sm.park[2][e] = make_float4(__int_as_float(ray), __int_as_float(k | (st << 16)), cx, cy);
+          ray = -1;
+        }
+        park_count = nsurv;
+        parked = true;
+      }
+    }
+    // refill freed slots: parked rays first, then the staging ring
+    if (!parked && park_count > 0) {
+      const unsigned long long fmask = __ballot(slot && ray < 0);
+      const int takep = min(__popcll(fmask), park_count);
+      const int p = __popcll(fmask & ((1ull << lane) - 1ull));
+      if (slot && ray < 0 && p < takep) {
+        const int e = (park_head + p) & (kPipeCols - 1);
+        const float4 r0 = sm.park[0][e], r1 = sm.park[1][e], r2 = sm.park[2][e];
+        ox = r0.x;
+        oy = r0.y;
+        oz = r0.z;
+        tau = r0.w;
+        vx = r1.x;
+        vy = r1.y;
+        vz = r1.z;
+        tt = r1.w;
+        ray = __float_as_int(r2.x);
+        k = __float_as_int(r2.y) & 0xFFFF;
+        st = __float_as_int(r2.y) >> 16;
+        cx = r2.z;
+        cy = r2.w;
+      }
+      park_head = (park_head + takep) & (kPipeCols - 1);
+      park_count -= takep;
+    }
     const unsigned long long emask = __ballot(slot && ray < 0);
     const int take = min(__popcll(emask), s_count);
     const int p = __popcll(emask & ((1ull << lane) - 1ull));
@@ -487,40 +543,34 @@ struct TraceCtl {
       tt = n_tt;
       tau = n_tau;
       k = 0;
+      center_at(A.B, tt, cx, cy);  // c(t) is fixed per ray: once, on entry
     }
     s_head = (s_head + take) & 63;
     s_count -= take;
-    top_up(A, lane);
+    // top up in batches of at least 32 entries: the loop and its queue atomics
+    // then run on a few stages only
+    if (s_count <= 32) top_up(A, lane);
     // inputs of tile s+1
     const bool live = __ballot(slot && ray >= 0) != 0ull;
     if (slot) {
-      sm.sray[G][sl] = ray;
-      sm.sk[G][sl] = k;
-      sm.sst[G][sl] = st;
-      sm.sf[0][G][sl] = tau;
-      sm.sf[1][G][sl] = ox;
-      sm.sf[2][G][sl] = oy;
-      sm.sf[3][G][sl] = oz;
-      sm.sf[4][G][sl] = vx;
-      sm.sf[5][G][sl] = vy;
-      sm.sf[6][G][sl] = vz;
-      sm.sf[7][G][sl] = tt;
-      float cx, cy;
-      center_at(A.B, tt, cx, cy);
+      sm.srec[G][0][sl] = make_float4(ox, oy, oz, tau);
+      sm.srec[G][1][sl] = make_float4(vx, vy, vz, tt);
+      sm.srec[G][2][sl] = make_float4(__int_as_float(ray), __int_as_float(k | (st << 16)), cx, cy);
       sm.xin[(s + 1) & 1][sl] = net_input(L, fmaf(tau, vx, ox), fmaf(tau, vy, oy), fmaf(tau, vz, oz), tt, cx, cy);
     }
-    if (lane == 0) pipe_publish(sm, s, G, live, s_count > 0 || !exhausted);
+    glive = live ? (glive | (1 << G)) : (glive & ~(1 << G));
+    if (lane == 0) pipe_publish(sm, s, glive, live, s_count > 0 || !exhausted || park_count > 0);
   }
 };
 
-// One team's side of the tracing kernel; TEAM2's role 4 runs the control.  The
+// One team's side of the tracing kernel; role 0 (team 1) runs the control.  The
 // two sides execute the same number of workgroup barriers.
 template <int P, bool RED, bool TEAM2>
 __device__ inline void trace_body(PipeSmem& sm, const TraceLevelArgs& A, int wave, int lane) {
   PipeWeights<P> W;
   W.load(A.L, wave, lane);
   const PipeLane pl = pipe_lane<false>(lane);
-  const bool ctl_wave = TEAM2 && wave == 4;
+  const bool ctl_wave = !TEAM2 && wave == 0;
   TraceCtl ctl;
   if (ctl_wave) {
     ctl.init(A);
@@ -533,10 +583,11 @@ __device__ inline void trace_body(PipeSmem& sm, const TraceLevelArgs& A, int wav
   for (int s = 0;; ++s) {
     if (sm.stop[(s + 1) & 1]) break;
     if (!TEAM2) {
-      pipe_team1<P, false, RED>(sm, W, A.L, acc, s, wave, pl);
+      pipe_team1_hidden<P, false, RED>(sm, W, acc, s, wave, pl);
+      if (ctl_wave) ctl.step(sm, A, s, lane);
+      pipe_team1_layer0<P, false, true>(sm, W, A.L, s, wave, pl);
     } else {
       pipe_team2_out<false, RED>(sm, acc, s, wave, pl);
-      if (ctl_wave) ctl.step(sm, A, s, lane);
       pipe_team2_in<P, false>(sm, W, A.L, acc, s, wave, pl);
     }
     __syncthreads();
@@ -557,7 +608,7 @@ __global__ void __launch_bounds__(kPipeThreads, 1) k_trace_ws(TraceLevelArgs A) 
 }
 
 // ---------------------------------------------------------------------------
-// Normal control (role 4): 8 points per group (columns 4 q + c), fetched ahead:
+// Normal control (role 0): 8 points per group (columns 4 q + c), fetched ahead:
 // in stage s the ray data of tile s+2 and the queue entries of tile s+3 are
 // loaded, so no stage waits on memory.
 struct NormalCtl {
@@ -565,6 +616,7 @@ struct NormalCtl {
   int q_ray;       // lanes 0..7: queue entries two tiles ahead
   int p_ray;       // lanes 0..7: rays of the next tile, with their data
   float p_ox, p_oy, p_oz, p_vx, p_vy, p_vz, p_tau, p_t;
+  int glive;  // bit G: slot group G holds points
 
   __device__ inline int fetch_id(const NormalArgs& A, int lane) {
     const int slot = next + lane;
@@ -587,6 +639,7 @@ struct NormalCtl {
   __device__ inline void init(const NormalArgs& A, int lane) {
     n_in = A.count ? *A.count : A.n;
     next = blockIdx.x * 8;
+    glive = 0;
     p_ox = p_oy = p_oz = p_vx = p_vy = p_vz = p_tau = p_t = 0.f;
     p_ray = fetch_id(A, lane);
     fetch_data(A);
@@ -599,16 +652,16 @@ struct NormalCtl {
     const bool col = lane < kPipeCols;
     const int q = (lane >> 2) & 7, c = lane & 3;
     // normals of tile s-4
-    if (sm.glive[G]) {
+    if (glive & (1 << G)) {
       const int pb = s & 1;
       const int sl = lane & (kPipeCols - 1);
       float val = sm.part[pb][0][sl] + sm.part[pb][1][sl] + sm.part[pb][2][sl] + sm.part[pb][3][sl];
       if (c == 0) val += L.bk;
       const float gx = quad_bcast<1>(val), gy = quad_bcast<2>(val), gz = quad_bcast<3>(val);
-      const int ray = sm.sray[G][q];
+      const int ray = __float_as_int(sm.srec[G][2][q].x);
       if (col && c == 0 && ray >= 0) {
-        const float x = sm.sf[0][G][q], y = sm.sf[1][G][q], z = sm.sf[2][G][q];
-        const float cx = sm.sf[3][G][q], cy = sm.sf[4][G][q];
+        const float4 r0 = sm.srec[G][0][q], r1 = sm.srec[G][1][q];
+        const float x = r0.x, y = r0.y, z = r0.z, cx = r1.x, cy = r1.y;
         float fx = L.amplitude * gx, fy = L.amplitude * gy, fz = L.amplitude * gz;
         if (A.B.sphere) {
           const float dx = x - cx, dy = y - cy;
@@ -636,12 +689,9 @@ struct NormalCtl {
     }
     const bool live = __ballot(p_ray >= 0) != 0ull;
     if (lane < 8) {
-      sm.sray[G][lane] = p_ray;
-      sm.sf[0][G][lane] = x;
-      sm.sf[1][G][lane] = y;
-      sm.sf[2][G][lane] = z;
-      sm.sf[3][G][lane] = cx;
-      sm.sf[4][G][lane] = cy;
+      sm.srec[G][0][lane] = make_float4(x, y, z, 0.f);
+      sm.srec[G][1][lane] = make_float4(cx, cy, 0.f, 0.f);
+      sm.srec[G][2][lane] = make_float4(__int_as_float(p_ray), 0.f, 0.f, 0.f);
     }
     const float qx = __shfl(x, q), qy = __shfl(y, q), qz = __shfl(z, q), qt = __shfl(p_t, q);
     const float qcx = __shfl(cx, q), qcy = __shfl(cy, q);
@@ -652,7 +702,8 @@ struct NormalCtl {
     q_ray = fetch_id(A, lane);
     // later tiles hold points only if tile s+2 does (tiles are fetched in slot order)
     const bool more = __ballot(p_ray >= 0) != 0ull;
-    if (lane == 0) pipe_publish(sm, s, G, live, more);
+    glive = live ? (glive | (1 << G)) : (glive & ~(1 << G));
+    if (lane == 0) pipe_publish(sm, s, glive, live, more);
   }
 };
 
@@ -661,7 +712,7 @@ __device__ inline void normal_body(PipeSmem& sm, const NormalArgs& A, int wave, 
   PipeWeights<P> W;
   W.load(A.L, wave, lane);
   const PipeLane pl = pipe_lane<true>(lane);
-  const bool ctl_wave = TEAM2 && wave == 4;
+  const bool ctl_wave = !TEAM2 && wave == 0;
   NormalCtl ctl;
   if (ctl_wave) ctl.init(A, lane);
   __syncthreads();
@@ -671,10 +722,11 @@ __device__ inline void normal_body(PipeSmem& sm, const NormalArgs& A, int wave, 
   for (int s = 0;; ++s) {
     if (sm.stop[(s + 1) & 1]) break;
     if (!TEAM2) {
-      pipe_team1<P, true, RED>(sm, W, A.L, acc, s, wave, pl);
+      pipe_team1_hidden<P, true, RED>(sm, W, acc, s, wave, pl);
+      if (ctl_wave) ctl.step(sm, A, s, lane);
+      pipe_team1_layer0<P, true, false>(sm, W, A.L, s, wave, pl);
     } else {
       pipe_team2_out<true, RED>(sm, acc, s, wave, pl);
-      if (ctl_wave) ctl.step(sm, A, s, lane);
       pipe_team2_in<P, true>(sm, W, A.L, acc, s, wave, pl);
     }
     __syncthreads();
