@@ -87,7 +87,8 @@ def run_form(scene, precision, o, v, t, steps, warmup):
             flops = hits * normal_hidden_flops(lvl.net)
             units = hits
         avg_ms = e["total_ms"] / max(e["launches"], 1)
-        kernels.append({"kind": e["kind"], "level": e["level"], "width": e["width"], "avg_ms": avg_ms,
+        kernels.append({"kind": e["kind"], "kernel": e["kernel"], "level": e["level"], "width": e["width"],
+                        "avg_ms": avg_ms,
                         "evals": units, "hidden_flops": flops,
                         "tflops": flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0})
     res = {"precision": precision, "ms_per_step": ms, "rays_per_s": n / (ms * 1e-3), "hits": hits,
@@ -130,13 +131,39 @@ def run_fit(steps, warmup):
             "final_loss4": [round(float(v_), 6) for v_ in loss.cpu().numpy()]}
 
 
+# HBM bytes per launch of the dominant kernel, from the FETCH_SIZE / WRITE_SIZE
+# counter passes summarised in profiles/ (bf16 form).  Used only while the
+# kernel's sources hash to the profiled build; otherwise the field is null.
+HBM_PROFILE = os.path.join(ROOT, "profiles", "trace_ws_stack3_1080p_hbm.txt")
+
+
+def measured_traffic(kernel, precision):
+    import hashlib
+    if kernel != "k_trace_ws" or precision != "bf16" or not os.path.exists(HBM_PROFILE):
+        return None
+    fields = {}
+    for line in open(HBM_PROFILE):
+        key, sep, val = line.partition(":")
+        if sep and key in ("traffic_bytes_per_launch", "kernel_sources_sha256_16", "kernel_sources"):
+            fields[key] = val.strip()
+    try:
+        h = hashlib.sha256()
+        for f in fields["kernel_sources"].split():
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest()[:16] != fields["kernel_sources_sha256_16"]:
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def roofline(form):
     dom = max(form["kernels"], key=lambda k: k["avg_ms"])
     peak = PEAK_TFLOPS[form["precision"]]
     return {"bound": "mfma", "achieved": round(dom["tflops"], 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(dom["tflops"] / peak, 5), "traffic": None,
-            "kernel": f"k_trace_level<{dom['width']}> level {dom['level']}" if dom["kind"] == "trace"
-            else f"k_normal<{dom['width']}>",
+            "frac": round(dom["tflops"] / peak, 5), "traffic": measured_traffic(dom["kernel"], form["precision"]),
+            "kernel": f"{dom['kernel']} (H={dom['width']}) level {dom['level']}",
             "avg_ms": round(dom["avg_ms"], 4), "flops_per_launch": dom["hidden_flops"]}
 
 
@@ -148,7 +175,7 @@ def main():
     ap.add_argument("--workload", default="stack3_1080p")
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--forms", default="fp32,bf16,fp16")
-    ap.add_argument("--cpu-rows-every", type=int, default=16)
+    ap.add_argument("--cpu-rows-every", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fit-steps", type=int, default=10, help="fitting steps to time (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",

@@ -248,7 +248,9 @@ int fit_set_step(nnm_fit* fit, int64_t step);
 /* A profiler records a HIP event pair around every kernel that trace_rays
    launches while it is attached to the trace parameters (events on the call's
    stream; no synchronisation until a report is requested).  Entries are keyed
-   by (kind, level): kind 0 = tracing of one level, 1 = normal pass. */
+   by (kind, level, variant): kind 0 = tracing of one level, 1 = normal pass;
+   variant 0 = single-wave streaming tile (k_trace_level / k_normal),
+   1 = pipelined weight-stationary workgroup (k_trace_ws / k_normal_ws). */
 #define NNM_PROF_MAX 32
 typedef struct {
   int32_t n_entries;
@@ -257,6 +259,7 @@ typedef struct {
   int32_t width[NNM_PROF_MAX];
   int64_t launches[NNM_PROF_MAX];
   double total_ms[NNM_PROF_MAX];
+  int32_t variant[NNM_PROF_MAX];
 } nnm_profile_report;
 
 int nnm_profiler_create(nnm_profiler** out);

@@ -46,7 +46,7 @@ _PROF_MAX = 32
 class _ProfileReport(ctypes.Structure):
     _fields_ = [("n_entries", c_int32), ("kind", c_int32 * _PROF_MAX), ("level", c_int32 * _PROF_MAX),
                 ("width", c_int32 * _PROF_MAX), ("launches", c_int64 * _PROF_MAX),
-                ("total_ms", c_double * _PROF_MAX)]
+                ("total_ms", c_double * _PROF_MAX), ("variant", c_int32 * _PROF_MAX)]
 
 
 _lib = None
@@ -243,12 +243,18 @@ class Profiler:
         _check(load_library().nnm_profiler_reset(self._h))
 
     def report(self):
-        """List of dicts (kind 'trace'/'normal', level, width, launches, total_ms)."""
+        """List of dicts (kind 'trace'/'normal', level, width, kernel, launches, total_ms)."""
         r = _ProfileReport()
         _check(load_library().nnm_profiler_report(self._h, ctypes.cast(ctypes.byref(r), c_void_p)))
-        return [{"kind": ("trace", "normal")[r.kind[i]], "level": r.level[i], "width": r.width[i],
-                 "launches": int(r.launches[i]), "total_ms": float(r.total_ms[i])}
-                for i in range(r.n_entries)]
+        names = {("trace", 0): "k_trace_level", ("trace", 1): "k_trace_ws",
+                 ("normal", 0): "k_normal", ("normal", 1): "k_normal_ws"}
+        out = []
+        for i in range(r.n_entries):
+            kind = ("trace", "normal")[r.kind[i]]
+            out.append({"kind": kind, "level": r.level[i], "width": r.width[i],
+                        "kernel": names[(kind, r.variant[i])],
+                        "launches": int(r.launches[i]), "total_ms": float(r.total_ms[i])})
+        return out
 
     def close(self):
         if self._h:

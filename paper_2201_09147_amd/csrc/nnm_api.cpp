@@ -162,7 +162,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct nnm_profiler {
   struct Rec {
-    int kind, level, width;
+    int kind, level, width, variant;
     hipEvent_t start, stop;
   };
   std::vector<Rec> recs;
@@ -196,11 +196,12 @@ struct ProfScope {
   nnm_profiler* p;
   nnm_profiler::Rec rec{};
   hipStream_t s;
-  ProfScope(nnm_profiler* prof, int kind, int level, int width, hipStream_t st) : p(prof), s(st) {
+  ProfScope(nnm_profiler* prof, int kind, int level, int width, int variant, hipStream_t st) : p(prof), s(st) {
     if (!p) return;
     rec.kind = kind;
     rec.level = level;
     rec.width = width;
+    rec.variant = variant;
     rec.start = p->get();
     rec.stop = p->get();
     if (rec.start) (void)hipEventRecord(rec.start, s);
@@ -570,8 +571,9 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
     a.eps = p->eps;
     a.far = p->far;
     a.delta = is_final ? 0.f : lv.delta;
-    ProfScope prof(p->profiler, 0, j, lv.width, st);
-    if (lv.dev.ws_ah && s->use_ws) {
+    const bool ws_kernel = lv.dev.ws_ah && s->use_ws;
+    ProfScope prof(p->profiler, 0, j, lv.width, ws_kernel ? 1 : 0, st);
+    if (ws_kernel) {
       const long long want = ((long long)n + kWsRaysPerBlock - 1) / kWsRaysPerBlock;
       const int grid = (int)std::max(1LL, std::min(want, (long long)lv.ws_resident[0]));
       if ((e = launch_trace_ws(s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "trace level (ws)");
@@ -594,8 +596,9 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
     a.queue = q[(L - 1) & 1];
     a.count = cnt + 2 * (L - 1) + 1;
     a.n = (int)n;
-    ProfScope prof(p->profiler, 1, p->normal_level, nl.width, st);
-    if (nl.dev.ws_ah && s->use_ws) {
+    const bool ws_kernel = nl.dev.ws_ah && s->use_ws;
+    ProfScope prof(p->profiler, 1, p->normal_level, nl.width, ws_kernel ? 1 : 0, st);
+    if (ws_kernel) {
       const long long want = ((long long)n + kWsPointsPerBlock - 1) / kWsPointsPerBlock;
       const int grid = (int)std::max(1LL, std::min(want, (long long)nl.ws_resident[1]));
       if ((e = launch_normal_ws(s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "normal pass (ws)");
@@ -675,13 +678,14 @@ int nnm_profiler_report(nnm_profiler* prof, nnm_profile_report* out) {
     if (e != hipSuccess) return hip_fail(e, "profiler elapsed time");
     int slot = -1;
     for (int i = 0; i < out->n_entries; ++i)
-      if (out->kind[i] == r.kind && out->level[i] == r.level) slot = i;
+      if (out->kind[i] == r.kind && out->level[i] == r.level && out->variant[i] == r.variant) slot = i;
     if (slot < 0) {
       if (out->n_entries >= NNM_PROF_MAX) continue;
       slot = out->n_entries++;
       out->kind[slot] = r.kind;
       out->level[slot] = r.level;
       out->width[slot] = r.width;
+      out->variant[slot] = r.variant;
     }
     out->launches[slot] += 1;
     out->total_ms[slot] += ms;

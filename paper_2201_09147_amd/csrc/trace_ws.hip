@@ -18,8 +18,8 @@
 //   * team 2 applies sin to its accumulators of tile s-3 and forms its part of
 //     the output dot product, then multiplies tile s-2 (act1) by its rows of
 //     W_2: VALU first, then MFMA;
-//   * role 0 (a team-1 wave, after its sines; when tracing, role 1 takes over
-//     its first-layer block) takes the outputs of tile s-4, runs the
+//   * role 0 (a team-1 wave, after its sines; role 1 takes over its
+//     first-layer block) takes the outputs of tile s-4, runs the
 //     Algorithm 1 update (or the normal's last step), retires finished rays,
 //     refills the freed slots and writes the inputs of tile s+1.
 // The two teams' MFMA and VALU phases are opposite, so each SIMD overlaps one
@@ -195,20 +195,22 @@ __device__ inline void pipe_store(const f32x16_t (&acc)[2], uint16_t* dst, int t
 }
 
 // sin of a team-2 wave's rows, dotted with the output weights in float32.
+// Four partial sums keep the fma chain short.
 template <bool TAN, bool RED>
 __device__ inline float pipe_dot(const f32x16_t (&acc)[2], const float* wk, int tw, const PipeLane& pl) {
-  float s = 0.f;
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
     for (int b4 = 0; b4 < 4; ++b4) {
       const float4 w = *(const float4*)&wk[64 * tw + 32 * rb + 8 * b4 + 4 * pl.g];
-      s = fmaf(w.x, pipe_act<TAN, RED>(acc[rb][4 * b4 + 0], pl), s);
-      s = fmaf(w.y, pipe_act<TAN, RED>(acc[rb][4 * b4 + 1], pl), s);
-      s = fmaf(w.z, pipe_act<TAN, RED>(acc[rb][4 * b4 + 2], pl), s);
-      s = fmaf(w.w, pipe_act<TAN, RED>(acc[rb][4 * b4 + 3], pl), s);
+      s[0] = fmaf(w.x, pipe_act<TAN, RED>(acc[rb][4 * b4 + 0], pl), s[0]);
+      s[1] = fmaf(w.y, pipe_act<TAN, RED>(acc[rb][4 * b4 + 1], pl), s[1]);
+      s[2] = fmaf(w.z, pipe_act<TAN, RED>(acc[rb][4 * b4 + 2], pl), s[2]);
+      s[3] = fmaf(w.w, pipe_act<TAN, RED>(acc[rb][4 * b4 + 3], pl), s[3]);
     }
-  return s + __shfl_xor(s, 32);
+  const float t = (s[0] + s[1]) + (s[2] + s[3]);
+  return t + __shfl_xor(t, 32);
 }
 
 __device__ inline void pipe_setup(PipeSmem& sm, const DevLevel& L) {
@@ -665,15 +667,16 @@ struct NormalCtl {
         float fx = L.amplitude * gx, fy = L.amplitude * gy, fz = L.amplitude * gz;
         if (A.B.sphere) {
           const float dx = x - cx, dy = y - cy;
-          const float r = sqrtf(fmaf(dx, dx, fmaf(dy, dy, z * z)));
-          if (r > 0.f) {
-            fx += dx / r;
-            fy += dy / r;
-            fz += z / r;
+          const float r2 = fmaf(dx, dx, fmaf(dy, dy, z * z));
+          if (r2 > 0.f) {
+            const float ir = rsqrtf(r2);
+            fx = fmaf(dx, ir, fx);
+            fy = fmaf(dy, ir, fy);
+            fz = fmaf(z, ir, fz);
           }
         }
-        const float len = sqrtf(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
-        const float inv = len > 0.f ? 1.f / len : 0.f;
+        const float len2 = fmaf(fx, fx, fmaf(fy, fy, fz * fz));
+        const float inv = len2 > 0.f ? rsqrtf(len2) : 0.f;
         A.normal[3 * ray + 0] = fx * inv;
         A.normal[3 * ray + 1] = fy * inv;
         A.normal[3 * ray + 2] = fz * inv;
@@ -724,7 +727,7 @@ __device__ inline void normal_body(PipeSmem& sm, const NormalArgs& A, int wave, 
     if (!TEAM2) {
       pipe_team1_hidden<P, true, RED>(sm, W, acc, s, wave, pl);
       if (ctl_wave) ctl.step(sm, A, s, lane);
-      pipe_team1_layer0<P, true, false>(sm, W, A.L, s, wave, pl);
+      pipe_team1_layer0<P, true, true>(sm, W, A.L, s, wave, pl);
     } else {
       pipe_team2_out<true, RED>(sm, acc, s, wave, pl);
       pipe_team2_in<P, true>(sm, W, A.L, acc, s, wave, pl);
