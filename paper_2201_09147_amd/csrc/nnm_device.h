@@ -33,7 +33,7 @@ constexpr int kSegments = 64;       // input queue segments, each with its own h
 constexpr int kHeadStride = 32;     // ints between segment heads (one 128-byte line each)
 constexpr int kPipeGroups = 5;       // slot groups in flight in a weight-stationary workgroup
 constexpr int kWsRaysPerBlock = 160;  // ray slots of a weight-stationary tracing workgroup
-constexpr int kWsPointsPerBlock = 40; // point slots of a weight-stationary normal workgroup
+constexpr int kWsPointsPerBlock = 80; // point slots of a weight-stationary normal workgroup
 
 // Index of the accumulator-layout slot (mb, g, r) in a [H] array.
 __host__ __device__ inline int acc_slot(int mb, int g, int r) { return (mb * 2 + g) * 16 + r; }

@@ -7,8 +7,9 @@
 // on).  Team 1 (waves 0-3) keeps rows [64 w, 64 w + 64)
 // of the first hidden weight matrix in registers for the whole kernel, team 2
 // (waves 4-7) the same rows of the second; the hidden weights are read from
-// memory once per workgroup.  Tiles of 32 columns (32 rays, or 8 points x
-// [h | G_x G_y G_z] for the normal) move through a software pipeline with one
+// memory once per workgroup.  Tiles of 64 columns (64 rays, or 16 points x
+// [h | G_x G_y G_z] for the normal; two 32-column MFMA blocks) move through a
+// software pipeline with one
 // workgroup barrier per stage.  In stage s:
 //   * every wave evaluates its 32-row block of the first sine layer of tile s
 //     (32x32x2 fp32 MFMA over (x, y, z[, t], 1), then sin) into act0[s % 2];
@@ -33,24 +34,29 @@
 namespace nnm {
 
 constexpr int kPipeThreads = 512;
-constexpr int kPipeCols = 32;         // columns per tile
+// Columns per tile: 32 for tracing (fewer rays in flight keeps the tiles full
+// while the last, longest rays finish), 64 for the normal pass (no iteration,
+// so twice the columns per control step is a straight gain).
+constexpr int kTraceCols = 32;
+constexpr int kNormalCols = 64;
 constexpr int kPipeStride = 256 + 8;  // 16-bit elements per LDS column (spreads LDS banks)
-constexpr int kParkMax = 16;          // most survivors a group parks (tail compaction)
+constexpr int kParkMax = kTraceCols / 2;  // most survivors a group parks (tail compaction)
 static_assert(kPipeGroups == 5, "tile t uses group t % 5: five tiles are in flight");
-static_assert(kPipeGroups * kPipeCols == kWsRaysPerBlock && kPipeGroups * 8 == kWsPointsPerBlock, "slots");
+static_assert(kPipeGroups * kTraceCols == kWsRaysPerBlock && kPipeGroups * kNormalCols / 4 == kWsPointsPerBlock, "slots");
 
+template <int C>
 struct PipeSmem {
-  uint16_t act0[2][kPipeCols * kPipeStride];
-  uint16_t act1[2][kPipeCols * kPipeStride];
+  uint16_t act0[2][C * kPipeStride];
+  uint16_t act1[2][C * kPipeStride];
   float bias[2][256];
   float zeros[256];
   float wk[256];
-  float part[2][4][kPipeCols];
-  float4 xin[2][kPipeCols];
+  float part[2][4][C];
+  float4 xin[2][C];
   // slot records, three float4 per slot: tracing {o, tau} {v, t} {ray, k | st << 16, c(t)};
   // normal {x, 0} {c(t), 0, 0} {ray, 0, 0, 0}
-  float4 srec[kPipeGroups][3][kPipeCols];
-  float4 park[3][kPipeCols];  // tracing: parked slot records (tail compaction)
+  float4 srec[kPipeGroups][3][C];
+  float4 park[3][C];  // tracing: parked slot records (tail compaction)
   int tlive[8];
   int stop[2];
   int simd_count[4];
@@ -134,32 +140,36 @@ __device__ inline void pipe_store4(uint16_t* dst, uint16_t h0, uint16_t h1, uint
 }
 
 // First sine layer, rows [32 blk, 32 blk + 32) of one tile (operand W.w0[slot]).
-template <int P, bool TAN>
+template <int C, int P, bool TAN>
 __device__ inline void pipe_layer0(const PipeWeights<P>& W, int slot, const float4* xin, uint16_t* dst, int d_in, int blk,
                                    const PipeLane& pl) {
-  const float4 in = xin[pl.j];
   const int ks0 = d_in == 4 ? 3 : 2;
-  f32x16_t acc;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  for (int cb = 0; cb < (C / 32); ++cb) {
+    const int col = 32 * cb + pl.j;
+    const float4 in = xin[col];
+    f32x16_t acc;
 #pragma unroll
-  for (int ks = 0; ks < 3; ++ks)
-    if (ks < ks0)
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(W.w0[slot][ks], layer0_input(in, d_in, pl.c, ks, pl.g), acc, 0, 0, 0);
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
 #pragma unroll
-  for (int b4 = 0; b4 < 4; ++b4) {
-    uint16_t h[4];
+    for (int ks = 0; ks < 3; ++ks)
+      if (ks < ks0)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(W.w0[slot][ks], layer0_input(in, d_in, pl.c, ks, pl.g), acc, 0, 0, 0);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) h[i] = PipeBits<P>::bits(pipe_act<TAN, true>(acc[4 * b4 + i], pl));
-    pipe_store4(&dst[pl.j * kPipeStride + 32 * blk + 8 * b4 + 4 * pl.g], h[0], h[1], h[2], h[3]);
+    for (int b4 = 0; b4 < 4; ++b4) {
+      uint16_t h[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[i] = PipeBits<P>::bits(pipe_act<TAN, true>(acc[4 * b4 + i], pl));
+      pipe_store4(&dst[col * kPipeStride + 32 * blk + 8 * b4 + 4 * pl.g], h[0], h[1], h[2], h[3]);
+    }
   }
 }
 
 // Hidden product of one team wave: acc = bias + W[rows] act (the caller passes
 // a zero bias for tangent columns).
-template <int P>
-__device__ inline void pipe_hidden(const PipeWeights<P>& W, const uint16_t* src, const float* bias, f32x16_t (&acc)[2],
-                                   int tw, const PipeLane& pl) {
+template <int C, int P>
+__device__ inline void pipe_hidden(const PipeWeights<P>& W, const uint16_t* src, const float* bias,
+                                   f32x16_t (&acc)[(C / 32)][2], int tw, const PipeLane& pl) {
   typedef HiddenOps<P> Ops;
   typedef typename Ops::frag_t frag_t;
 #pragma unroll
@@ -167,31 +177,42 @@ __device__ inline void pipe_hidden(const PipeWeights<P>& W, const uint16_t* src,
 #pragma unroll
     for (int b4 = 0; b4 < 4; ++b4) {
       const float4 b = *(const float4*)&bias[64 * tw + 32 * rb + 8 * b4 + 4 * pl.g];
-      acc[rb][4 * b4 + 0] = b.x;
-      acc[rb][4 * b4 + 1] = b.y;
-      acc[rb][4 * b4 + 2] = b.z;
-      acc[rb][4 * b4 + 3] = b.w;
+#pragma unroll
+      for (int cb = 0; cb < (C / 32); ++cb) {
+        acc[cb][rb][4 * b4 + 0] = b.x;
+        acc[cb][rb][4 * b4 + 1] = b.y;
+        acc[cb][rb][4 * b4 + 2] = b.z;
+        acc[cb][rb][4 * b4 + 3] = b.w;
+      }
     }
 #pragma unroll
   for (int ks = 0; ks < 16; ++ks) {
-    const frag_t b = *(const frag_t*)&src[pl.j * kPipeStride + 16 * ks + 8 * pl.g];
+    frag_t b[(C / 32)];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) acc[rb] = Ops::mfma(W.w[rb][ks], b, acc[rb]);
+    for (int cb = 0; cb < (C / 32); ++cb)
+      b[cb] = *(const frag_t*)&src[(32 * cb + pl.j) * kPipeStride + 16 * ks + 8 * pl.g];
+#pragma unroll
+    for (int cb = 0; cb < (C / 32); ++cb)
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) acc[cb][rb] = Ops::mfma(W.w[rb][ks], b[cb], acc[cb][rb]);
   }
 }
 
 // sin of a team-1 wave's rows into the next layer's activations.
-template <int P, bool TAN, bool RED>
-__device__ inline void pipe_store(const f32x16_t (&acc)[2], uint16_t* dst, int tw, const PipeLane& pl) {
+template <int C, int P, bool TAN, bool RED>
+__device__ inline void pipe_store(const f32x16_t (&acc)[(C / 32)][2], uint16_t* dst, int tw, const PipeLane& pl) {
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
+  for (int cb = 0; cb < (C / 32); ++cb)
 #pragma unroll
-    for (int b4 = 0; b4 < 4; ++b4) {
-      uint16_t h[4];
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) h[i] = PipeBits<P>::bits(pipe_act<TAN, RED>(acc[rb][4 * b4 + i], pl));
-      pipe_store4(&dst[pl.j * kPipeStride + 64 * tw + 32 * rb + 8 * b4 + 4 * pl.g], h[0], h[1], h[2], h[3]);
-    }
+      for (int b4 = 0; b4 < 4; ++b4) {
+        uint16_t h[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[i] = PipeBits<P>::bits(pipe_act<TAN, RED>(acc[cb][rb][4 * b4 + i], pl));
+        pipe_store4(&dst[(32 * cb + pl.j) * kPipeStride + 64 * tw + 32 * rb + 8 * b4 + 4 * pl.g], h[0], h[1], h[2],
+                    h[3]);
+      }
 }
 
 // sin of a team-2 wave's rows, dotted with the output weights in float32.
@@ -211,17 +232,18 @@ __device__ inline float pipe_dot(const f32x16_t (&acc)[2], const float* wk, int 
     }
   const float t = (s[0] + s[1]) + (s[2] + s[3]);
   return t + __shfl_xor(t, 32);
-}
+}  // (one 32-column block; callers loop over the tile's blocks)
 
-__device__ inline void pipe_setup(PipeSmem& sm, const DevLevel& L) {
+template <int C>
+__device__ inline void pipe_setup(PipeSmem<C>& sm, const DevLevel& L) {
   for (int i = threadIdx.x; i < 256; i += kPipeThreads) {
     sm.bias[0][i] = L.bh_plain[i];
     sm.bias[1][i] = L.bh_plain[256 + i];
     sm.wk[i] = L.wk_plain[i];
     sm.zeros[i] = 0.f;
   }
-  for (int i = threadIdx.x; i < kPipeGroups * kPipeCols; i += kPipeThreads)
-    sm.srec[i / kPipeCols][2][i % kPipeCols] = make_float4(__int_as_float(-1), 0.f, 0.f, 0.f);
+  for (int i = threadIdx.x; i < kPipeGroups * C; i += kPipeThreads)
+    sm.srec[i / C][2][i % C] = make_float4(__int_as_float(-1), 0.f, 0.f, 0.f);
   if (threadIdx.x < 8) sm.tlive[threadIdx.x] = 0;
   if (threadIdx.x < 2) sm.stop[threadIdx.x] = 0;
   if (threadIdx.x < 4) sm.simd_count[threadIdx.x] = 0;
@@ -232,7 +254,8 @@ __device__ inline void pipe_setup(PipeSmem& sm, const DevLevel& L) {
 // placement the dispatcher chose.  (Eight waves of 256 registers fill the four
 // register files exactly, so each SIMD holds two of them; if the counts say
 // otherwise the wave index decides.)  Contains a workgroup barrier.
-__device__ inline int pipe_role(PipeSmem& sm) {
+template <int C>
+__device__ inline int pipe_role(PipeSmem<C>& sm) {
   const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     // HW_ID bits [5:4]: the SIMD this wave runs on
@@ -250,58 +273,65 @@ __device__ inline int pipe_role(PipeSmem& sm) {
 // the control in between).  Team 2 in two calls: the output sines of tile s-3,
 // then its first-layer block of tile s and the second hidden product of tile
 // s-2, whose accumulators carry into stage s+1.
-template <int P, bool TAN, bool RED>
-__device__ inline void pipe_team1_hidden(PipeSmem& sm, const PipeWeights<P>& W, f32x16_t (&acc)[2], int s, int wave,
-                                         const PipeLane& pl) {
+template <int C, int P, bool TAN, bool RED>
+__device__ inline void pipe_team1_hidden(PipeSmem<C>& sm, const PipeWeights<P>& W, f32x16_t (&acc)[(C / 32)][2], int s,
+                                         int wave, const PipeLane& pl) {
   if (sm.tlive[(s + 7) & 7]) {
-    pipe_hidden<P>(W, sm.act0[(s + 1) & 1], (TAN && pl.c) ? sm.zeros : sm.bias[0], acc, wave & 3, pl);
-    pipe_store<P, TAN, RED>(acc, sm.act1[(s + 1) & 1], wave & 3, pl);
+    pipe_hidden<C, P>(W, sm.act0[(s + 1) & 1], (TAN && pl.c) ? sm.zeros : sm.bias[0], acc, wave & 3, pl);
+    pipe_store<C, P, TAN, RED>(acc, sm.act1[(s + 1) & 1], wave & 3, pl);
   }
 }
 
 // OFF0: role 0 (the control wave) hands its first-layer block to role 1.
-template <int P, bool TAN, bool OFF0>
-__device__ inline void pipe_team1_layer0(PipeSmem& sm, const PipeWeights<P>& W, const DevLevel& L, int s, int wave,
+template <int C, int P, bool TAN, bool OFF0>
+__device__ inline void pipe_team1_layer0(PipeSmem<C>& sm, const PipeWeights<P>& W, const DevLevel& L, int s, int wave,
                                          const PipeLane& pl) {
   if (!sm.tlive[s & 7]) return;
-  if (!OFF0 || wave != 0) pipe_layer0<P, TAN>(W, 0, sm.xin[s & 1], sm.act0[s & 1], L.d_in, wave, pl);
-  if (OFF0 && wave == 1) pipe_layer0<P, TAN>(W, 1, sm.xin[s & 1], sm.act0[s & 1], L.d_in, 0, pl);
+  if (!OFF0 || wave != 0) pipe_layer0<C, P, TAN>(W, 0, sm.xin[s & 1], sm.act0[s & 1], L.d_in, wave, pl);
+  if (OFF0 && wave == 1) pipe_layer0<C, P, TAN>(W, 1, sm.xin[s & 1], sm.act0[s & 1], L.d_in, 0, pl);
 }
 
-template <bool TAN, bool RED>
-__device__ inline void pipe_team2_out(PipeSmem& sm, const f32x16_t (&acc)[2], int s, int wave, const PipeLane& pl) {
+template <int C, bool TAN, bool RED>
+__device__ inline void pipe_team2_out(PipeSmem<C>& sm, const f32x16_t (&acc)[(C / 32)][2], int s, int wave,
+                                      const PipeLane& pl) {
   const int tw = wave & 3;
   if (sm.tlive[(s + 5) & 7]) {
-    const float p = pipe_dot<TAN, RED>(acc, sm.wk, tw, pl);
-    if (pl.g == 0) sm.part[(s + 1) & 1][tw][pl.j] = p;
+#pragma unroll
+    for (int cb = 0; cb < (C / 32); ++cb) {
+      const float p = pipe_dot<TAN, RED>(acc[cb], sm.wk, tw, pl);
+      if (pl.g == 0) sm.part[(s + 1) & 1][tw][32 * cb + pl.j] = p;
+    }
   }
 }
 
-template <int P, bool TAN>
-__device__ inline void pipe_team2_in(PipeSmem& sm, const PipeWeights<P>& W, const DevLevel& L, f32x16_t (&acc)[2], int s,
-                                     int wave, const PipeLane& pl) {
+template <int C, int P, bool TAN>
+__device__ inline void pipe_team2_in(PipeSmem<C>& sm, const PipeWeights<P>& W, const DevLevel& L,
+                                     f32x16_t (&acc)[(C / 32)][2], int s, int wave, const PipeLane& pl) {
   const int tw = wave & 3;
-  if (sm.tlive[s & 7]) pipe_layer0<P, TAN>(W, 0, sm.xin[s & 1], sm.act0[s & 1], L.d_in, wave, pl);
+  if (sm.tlive[s & 7]) pipe_layer0<C, P, TAN>(W, 0, sm.xin[s & 1], sm.act0[s & 1], L.d_in, wave, pl);
   if (sm.tlive[(s + 6) & 7]) {
-    pipe_hidden<P>(W, sm.act1[s & 1], (TAN && pl.c) ? sm.zeros : sm.bias[1], acc, tw, pl);
+    pipe_hidden<C, P>(W, sm.act1[s & 1], (TAN && pl.c) ? sm.zeros : sm.bias[1], acc, tw, pl);
   } else {
     // overwritten on both paths: the accumulators are dead between the two calls
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int cb = 0; cb < (C / 32); ++cb)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[rb][r] = 0.f;
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[cb][rb][r] = 0.f;
   }
 }
 
 // Tile liveness and the stop flag, written by lane 0 of the control wave;
 // glive is the control wave's bitmask of groups holding rays.
-__device__ inline void pipe_publish(PipeSmem& sm, int s, int glive, bool live, bool more) {
+template <int C>
+__device__ inline void pipe_publish(PipeSmem<C>& sm, int s, int glive, bool live, bool more) {
   sm.tlive[(s + 1) & 7] = live ? 1 : 0;
   sm.stop[(s + 2) & 1] = (glive == 0 && !more) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
-// Tracing control (role 0): 32 ray slots per group, one per lane 0..31, and a
+// Tracing control (role 0): 64 ray slots per group, one per lane, and a
 // 64-entry staging ring of prefetched rays (lane e holds entry e) that refills
 // freed slots by lane shuffles and is topped up right after, so its loads
 // complete while the pipeline runs.
@@ -376,7 +406,7 @@ struct TraceCtl {
     }
   }
 
-  __device__ inline void push(PipeSmem& sm, const TraceLevelArgs& A, int lane, bool hit, int ray) {
+  __device__ inline void push(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int lane, bool hit, int ray) {
     const unsigned long long pmask = __ballot(hit);
     if (!pmask || !A.out_queue) return;
     if (hit) sm.ring[(ring_start + ring_n + __popcll(pmask & ((1ull << lane) - 1ull))) & (2 * kPushBatch - 1)] = ray;
@@ -393,7 +423,7 @@ struct TraceCtl {
     }
   }
 
-  __device__ inline void flush(PipeSmem& sm, const TraceLevelArgs& A, int lane) {
+  __device__ inline void flush(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int lane) {
     if (ring_n == 0 || !A.out_queue) return;
     __builtin_amdgcn_wave_barrier();
     int base = 0;
@@ -403,11 +433,11 @@ struct TraceCtl {
   }
 
   // Stage s (s = -1: prologue): finish tile s-4, refill its group, write tile s+1.
-  __device__ inline void step(PipeSmem& sm, const TraceLevelArgs& A, int s, int lane) {
+  __device__ inline void step(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int s, int lane) {
     const DevLevel& L = A.L;
     const int G = (s + 1) % kPipeGroups;
-    const bool slot = lane < kPipeCols;
-    const int sl = lane & (kPipeCols - 1);
+    const bool slot = lane < kTraceCols;
+    const int sl = lane & (kTraceCols - 1);
     int ray = -1, k = 0, st = 0;
     float tau = 0.f, ox = 0.f, oy = 0.f, oz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, tt = 0.f, cx = 0.f, cy = 0.f;
     if (slot) {
@@ -489,7 +519,7 @@ struct TraceCtl {
       const int nsurv = __popcll(smask);
       if (nsurv > 0 && nsurv <= kParkMax) {
         if (slot && ray >= 0) {
-          const int e = (park_head + __popcll(smask & ((1ull << lane) - 1ull))) & (kPipeCols - 1);
+          const int e = (park_head + __popcll(smask & ((1ull << lane) - 1ull))) & (kTraceCols - 1);
           sm.park[0][e] = make_float4(ox, oy, oz, tau);
           sm.park[1][e] = make_float4(vx, vy, vz, tt);
           sm.park[2][e] = make_float4(__int_as_float(ray), __int_as_float(k | (st << 16)), cx, cy);
@@ -505,7 +535,7 @@ struct TraceCtl {
       const int takep = min(__popcll(fmask), park_count);
       const int p = __popcll(fmask & ((1ull << lane) - 1ull));
       if (slot && ray < 0 && p < takep) {
-        const int e = (park_head + p) & (kPipeCols - 1);
+        const int e = (park_head + p) & (kTraceCols - 1);
         const float4 r0 = sm.park[0][e], r1 = sm.park[1][e], r2 = sm.park[2][e];
         ox = r0.x;
         oy = r0.y;
@@ -521,7 +551,7 @@ struct TraceCtl {
         cx = r2.z;
         cy = r2.w;
       }
-      park_head = (park_head + takep) & (kPipeCols - 1);
+      park_head = (park_head + takep) & (kTraceCols - 1);
       park_count -= takep;
     }
     const unsigned long long emask = __ballot(slot && ray < 0);
@@ -568,7 +598,7 @@ struct TraceCtl {
 // One team's side of the tracing kernel; role 0 (team 1) runs the control.  The
 // two sides execute the same number of workgroup barriers.
 template <int P, bool RED, bool TEAM2>
-__device__ inline void trace_body(PipeSmem& sm, const TraceLevelArgs& A, int wave, int lane) {
+__device__ inline void trace_body(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int wave, int lane) {
   PipeWeights<P> W;
   W.load(A.L, wave, lane);
   const PipeLane pl = pipe_lane<false>(lane);
@@ -581,16 +611,16 @@ __device__ inline void trace_body(PipeSmem& sm, const TraceLevelArgs& A, int wav
   __syncthreads();
   if (ctl_wave) ctl.step(sm, A, -1, lane);
   __syncthreads();
-  f32x16_t acc[2];
+  f32x16_t acc[kTraceCols / 32][2];
   for (int s = 0;; ++s) {
     if (sm.stop[(s + 1) & 1]) break;
     if (!TEAM2) {
-      pipe_team1_hidden<P, false, RED>(sm, W, acc, s, wave, pl);
+      pipe_team1_hidden<kTraceCols, P, false, RED>(sm, W, acc, s, wave, pl);
       if (ctl_wave) ctl.step(sm, A, s, lane);
-      pipe_team1_layer0<P, false, true>(sm, W, A.L, s, wave, pl);
+      pipe_team1_layer0<kTraceCols, P, false, true>(sm, W, A.L, s, wave, pl);
     } else {
-      pipe_team2_out<false, RED>(sm, acc, s, wave, pl);
-      pipe_team2_in<P, false>(sm, W, A.L, acc, s, wave, pl);
+      pipe_team2_out<kTraceCols, false, RED>(sm, acc, s, wave, pl);
+      pipe_team2_in<kTraceCols, P, false>(sm, W, A.L, acc, s, wave, pl);
     }
     __syncthreads();
   }
@@ -599,7 +629,7 @@ __device__ inline void trace_body(PipeSmem& sm, const TraceLevelArgs& A, int wav
 
 template <int P, bool RED>
 __global__ void __launch_bounds__(kPipeThreads, 1) k_trace_ws(TraceLevelArgs A) {
-  __shared__ PipeSmem sm;
+  __shared__ PipeSmem<kTraceCols> sm;
   pipe_setup(sm, A.L);
   __syncthreads();
   const int wave = pipe_role(sm);
@@ -610,20 +640,20 @@ __global__ void __launch_bounds__(kPipeThreads, 1) k_trace_ws(TraceLevelArgs A) 
 }
 
 // ---------------------------------------------------------------------------
-// Normal control (role 0): 8 points per group (columns 4 q + c), fetched ahead:
+// Normal control (role 0): 16 points per group (columns 4 q + c), fetched ahead:
 // in stage s the ray data of tile s+2 and the queue entries of tile s+3 are
 // loaded, so no stage waits on memory.
 struct NormalCtl {
   int n_in, next;  // next: first queue slot of the next tile this workgroup fetches
-  int q_ray;       // lanes 0..7: queue entries two tiles ahead
-  int p_ray;       // lanes 0..7: rays of the next tile, with their data
+  int q_ray;       // lanes 0..15: queue entries two tiles ahead
+  int p_ray;       // lanes 0..15: rays of the next tile, with their data
   float p_ox, p_oy, p_oz, p_vx, p_vy, p_vz, p_tau, p_t;
   int glive;  // bit G: slot group G holds points
 
   __device__ inline int fetch_id(const NormalArgs& A, int lane) {
     const int slot = next + lane;
-    const int r = (lane < 8 && slot < n_in) ? (A.queue ? A.queue[slot] : slot) : -1;
-    next += 8 * gridDim.x;
+    const int r = (lane < (kNormalCols / 4) && slot < n_in) ? (A.queue ? A.queue[slot] : slot) : -1;
+    next += (kNormalCols / 4) * gridDim.x;
     return r;
   }
   __device__ inline void fetch_data(const NormalArgs& A) {
@@ -640,7 +670,7 @@ struct NormalCtl {
   }
   __device__ inline void init(const NormalArgs& A, int lane) {
     n_in = A.count ? *A.count : A.n;
-    next = blockIdx.x * 8;
+    next = blockIdx.x * (kNormalCols / 4);
     glive = 0;
     p_ox = p_oy = p_oz = p_vx = p_vy = p_vz = p_tau = p_t = 0.f;
     p_ray = fetch_id(A, lane);
@@ -648,15 +678,15 @@ struct NormalCtl {
     q_ray = fetch_id(A, lane);
   }
 
-  __device__ inline void step(PipeSmem& sm, const NormalArgs& A, int s, int lane) {
+  __device__ inline void step(PipeSmem<kNormalCols>& sm, const NormalArgs& A, int s, int lane) {
     const DevLevel& L = A.L;
     const int G = (s + 1) % kPipeGroups;
-    const bool col = lane < kPipeCols;
-    const int q = (lane >> 2) & 7, c = lane & 3;
+    const bool col = lane < kNormalCols;
+    const int q = (lane >> 2) & ((kNormalCols / 4) - 1), c = lane & 3;
     // normals of tile s-4
     if (glive & (1 << G)) {
       const int pb = s & 1;
-      const int sl = lane & (kPipeCols - 1);
+      const int sl = lane & (kNormalCols - 1);
       float val = sm.part[pb][0][sl] + sm.part[pb][1][sl] + sm.part[pb][2][sl] + sm.part[pb][3][sl];
       if (c == 0) val += L.bk;
       const float gx = quad_bcast<1>(val), gy = quad_bcast<2>(val), gz = quad_bcast<3>(val);
@@ -682,7 +712,7 @@ struct NormalCtl {
         A.normal[3 * ray + 2] = fz * inv;
       }
     }
-    // tile s+1 from the prefetched points (lanes 0..7)
+    // tile s+1 from the prefetched points (lanes 0..15)
     float x = 0.f, y = 0.f, z = 0.f, cx = 0.f, cy = 0.f;
     if (p_ray >= 0) {
       x = fmaf(p_tau, p_vx, p_ox);
@@ -691,7 +721,7 @@ struct NormalCtl {
       center_at(A.B, p_t, cx, cy);
     }
     const bool live = __ballot(p_ray >= 0) != 0ull;
-    if (lane < 8) {
+    if (lane < (kNormalCols / 4)) {
       sm.srec[G][0][lane] = make_float4(x, y, z, 0.f);
       sm.srec[G][1][lane] = make_float4(cx, cy, 0.f, 0.f);
       sm.srec[G][2][lane] = make_float4(__int_as_float(p_ray), 0.f, 0.f, 0.f);
@@ -711,7 +741,7 @@ struct NormalCtl {
 };
 
 template <int P, bool RED, bool TEAM2>
-__device__ inline void normal_body(PipeSmem& sm, const NormalArgs& A, int wave, int lane) {
+__device__ inline void normal_body(PipeSmem<kNormalCols>& sm, const NormalArgs& A, int wave, int lane) {
   PipeWeights<P> W;
   W.load(A.L, wave, lane);
   const PipeLane pl = pipe_lane<true>(lane);
@@ -721,16 +751,16 @@ __device__ inline void normal_body(PipeSmem& sm, const NormalArgs& A, int wave, 
   __syncthreads();
   if (ctl_wave) ctl.step(sm, A, -1, lane);
   __syncthreads();
-  f32x16_t acc[2];
+  f32x16_t acc[kNormalCols / 32][2];
   for (int s = 0;; ++s) {
     if (sm.stop[(s + 1) & 1]) break;
     if (!TEAM2) {
-      pipe_team1_hidden<P, true, RED>(sm, W, acc, s, wave, pl);
+      pipe_team1_hidden<kNormalCols, P, true, RED>(sm, W, acc, s, wave, pl);
       if (ctl_wave) ctl.step(sm, A, s, lane);
-      pipe_team1_layer0<P, true, true>(sm, W, A.L, s, wave, pl);
+      pipe_team1_layer0<kNormalCols, P, true, true>(sm, W, A.L, s, wave, pl);
     } else {
-      pipe_team2_out<true, RED>(sm, acc, s, wave, pl);
-      pipe_team2_in<P, true>(sm, W, A.L, acc, s, wave, pl);
+      pipe_team2_out<kNormalCols, true, RED>(sm, acc, s, wave, pl);
+      pipe_team2_in<kNormalCols, P, true>(sm, W, A.L, acc, s, wave, pl);
     }
     __syncthreads();
   }
@@ -738,7 +768,7 @@ __device__ inline void normal_body(PipeSmem& sm, const NormalArgs& A, int wave, 
 
 template <int P, bool RED>
 __global__ void __launch_bounds__(kPipeThreads, 1) k_normal_ws(NormalArgs A) {
-  __shared__ PipeSmem sm;
+  __shared__ PipeSmem<kNormalCols> sm;
   pipe_setup(sm, A.L);
   __syncthreads();
   const int wave = pipe_role(sm);
