@@ -47,7 +47,11 @@ def run_form(scene, precision, o, v, t, steps, warmup):
     import paper_2201_09147_amd as nnm
     dev = torch.device("cuda", 0)
     n = o.shape[0]
-    stack = nnm.load_siren_stack(scene, precision, 0)
+    torch.cuda.synchronize()
+    l0 = time.perf_counter()
+    stack = nnm.load_siren_stack(scene, precision, 0)  # validation, packing, upload: outside the timed region
+    torch.cuda.synchronize()
+    load_ms = (time.perf_counter() - l0) * 1e3
     out = {
         "depth": torch.empty(n, dtype=torch.float32, device=dev),
         "hit": torch.empty(n, dtype=torch.uint8, device=dev),
@@ -67,14 +71,24 @@ def run_form(scene, precision, o, v, t, steps, warmup):
     torch.cuda.synchronize()
     log(f"[{precision}] warmup done ({warmup} steps)")
     timed = nnm.TraceParams(scene.step_scale, scene.eps, scene.far, scene.max_steps, profiler=prof)
+    # per-call HIP events on the calls' (current) stream, plus the wall clock around all K calls
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
+        evs[i][0].record()
         call(timed)
+        evs[i][1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / steps
+    per_call = sorted(a.elapsed_time(b) for a, b in evs)
+    timing = {"median_ms": round(per_call[len(per_call) // 2], 4), "min_ms": round(per_call[0], 4),
+              "p90_ms": round(per_call[min(len(per_call) - 1, int(0.9 * len(per_call)))], 4),
+              "load_ms": round(load_ms, 3)}
     report = prof.report()
-    log(f"[{precision}] {steps} steps: {ms:.3f} ms/step, {n / ms * 1e3 / 1e9:.3f} Grays/s")
+    log(f"[{precision}] {steps} steps: {ms:.3f} ms/step, {n / ms * 1e3 / 1e9:.3f} Grays/s; per call median "
+        f"{timing['median_ms']:.3f} min {timing['min_ms']:.3f} p90 {timing['p90_ms']:.3f} ms; "
+        f"stack load {load_ms:.1f} ms")
     evals = out["steps"].to(torch.int64).sum(dim=0).cpu().tolist()
     hits = int(out["hit"].to(torch.int64).sum().item())
     kernels = []
@@ -91,7 +105,7 @@ def run_form(scene, precision, o, v, t, steps, warmup):
                         "avg_ms": avg_ms,
                         "evals": units, "hidden_flops": flops,
                         "tflops": flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0})
-    res = {"precision": precision, "ms_per_step": ms, "rays_per_s": n / (ms * 1e-3), "hits": hits,
+    res = {"precision": precision, "ms_per_step": ms, "rays_per_s": n / (ms * 1e-3), "hits": hits, "timing": timing,
            "evals_per_level": evals, "kernels": kernels,
            "outputs": {k: v_.cpu().numpy() for k, v_ in out.items()}}
     prof.close()
@@ -226,10 +240,17 @@ def main():
         c0 = time.perf_counter()
         ref = orc.trace(scene, o_np[idx], v_np[idx], None if t_np is None else t_np[idx])
         c1 = time.perf_counter()
+        # one core, on every 16th ray of the same sample
+        idx1 = idx[::16]
+        c2 = time.perf_counter()
+        orc.trace(scene, o_np[idx1], v_np[idx1], None if t_np is None else t_np[idx1], threads=1)
+        c3 = time.perf_counter()
         cpu = {"value": round(idx.size / (c1 - c0), 1), "unit": "rays/s", "cores": threads, "kind": "oracle",
                "sample": f"every {args.cpu_rows_every}th row of the {scene.width}x{scene.height} frame "
-                         f"({idx.size} rays), FP64, {c1 - c0:.1f} s"}
-        log(f"oracle: {cpu['value']} rays/s")
+                         f"({idx.size} rays), FP64, {c1 - c0:.1f} s",
+               "value_1core": round(idx1.size / (c3 - c2), 1),
+               "sample_1core": f"every 16th ray of that sample ({idx1.size} rays), 1 thread, {c3 - c2:.1f} s"}
+        log(f"oracle: {cpu['value']} rays/s on {threads} threads, {cpu['value_1core']} rays/s on 1")
         for f, r in results.items():
             g = {k: val[idx] for k, val in r["outputs"].items()}
             hit, rhit = g["hit"] == 1, ref["hit"] == 1
@@ -265,7 +286,10 @@ def main():
         "cpu_baseline": cpu,
         "errors_vs_oracle": errors,
         "fit": fit,
+        "timing": head["timing"],
+        "rays_per_s_median_call": round(n / (head["timing"]["median_ms"] * 1e-3), 1),
         "forms": {f: {"rays_per_s": round(r["rays_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                      "timing": r["timing"],
                       "roofline": roofline(r), "hits": r["hits"], "evals_per_level": r["evals_per_level"],
                       "frame_mfma_frac": round(sum(k["hidden_flops"] for k in r["kernels"])
                                                / (r["ms_per_step"] * 1e-3) / 1e12

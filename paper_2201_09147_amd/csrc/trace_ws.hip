@@ -4,13 +4,12 @@
 //
 // A workgroup is eight waves in two teams, one workgroup per CU, and every SIMD
 // holds one wave of each team (roles are assigned from the SIMD each wave runs
-// on).  Team 1 (waves 0-3) keeps rows [64 w, 64 w + 64)
-// of the first hidden weight matrix in registers for the whole kernel, team 2
-// (waves 4-7) the same rows of the second; the hidden weights are read from
-// memory once per workgroup.  Tiles of 64 columns (64 rays, or 16 points x
-// [h | G_x G_y G_z] for the normal; two 32-column MFMA blocks) move through a
-// software pipeline with one
-// workgroup barrier per stage.  In stage s:
+// on).  Team 1 (waves 0-3) keeps rows [64 w, 64 w + 64) of the first hidden
+// weight matrix in registers for the whole kernel, team 2 (waves 4-7) the same
+// rows of the second; the hidden weights are read from memory once per
+// workgroup.  Tiles of 32 columns (32 rays) when tracing, 64 columns (16 points
+// x [h | G_x G_y G_z], two 32-column MFMA blocks) in the normal pass, move
+// through a software pipeline with one workgroup barrier per stage.  In stage s:
 //   * every wave evaluates its 32-row block of the first sine layer of tile s
 //     (32x32x2 fp32 MFMA over (x, y, z[, t], 1), then sin) into act0[s % 2];
 //   * team 1 multiplies tile s-1 (act0) by its rows of W_1 (32x32x16 MFMAs,

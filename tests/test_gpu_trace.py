@@ -91,6 +91,42 @@ def test_stack3_1080p_full_image_sampled_rows():
     del torch
 
 
+def test_stack3_4096sq_stress_sampled_rows():
+    """The 4096x4096 stress run (16.8 M rays) in one call, bf16; every 256th
+    row checked against the oracle ray by ray, whole-frame invariants on all."""
+    s = ni.make_scene("stack3_4096sq")
+    o, v, _ = s.rays()
+    g = gpu_trace(s, o, v, precision="bf16")
+    rows = np.arange(17, 4096, 256)
+    idx = (rows[:, None] * 4096 + np.arange(4096)[None, :]).reshape(-1)
+    r = orc.trace(s, o[idx], v[idx])
+    sub = {k: (val[idx] if val is not None else None) for k, val in g.items()}
+    st = compare(sub, r)
+    _report("stack3 4096^2 full, sampled rows, bf16", st)
+    check_lowp(st)
+    hit = g["hit"] == 1
+    assert np.all((g["status"] & (nnm.ST_HIT | nnm.ST_FAR | nnm.ST_BUDGET | nnm.ST_NONFINITE)) != 0)
+    assert np.all(np.isinf(g["depth"][~hit])) and np.all(np.isfinite(g["depth"][hit]))
+    np.testing.assert_allclose(np.linalg.norm(g["normal"][hit], axis=1), 1.0, atol=1e-5)
+
+
+def test_anim16_all_frames_one_launch():
+    """All 16 frames of the animated scene (16 x 1024^2 rays) in one call, bf16;
+    sampled rows of every frame checked against the oracle."""
+    s = ni.make_scene("anim16_1024sq")
+    o, v, t = s.rays()
+    g = gpu_trace(s, o, v, t, precision="bf16")
+    n_frame = 1024 * 1024
+    rows = np.arange(11, 1024, 128)
+    idx = np.concatenate([f * n_frame + (rows[:, None] * 1024 + np.arange(1024)[None, :]).reshape(-1)
+                          for f in range(16)])
+    r = orc.trace(s, o[idx], v[idx], t[idx])
+    sub = {k: (val[idx] if val is not None else None) for k, val in g.items()}
+    st = compare(sub, r)
+    _report("anim16 all frames, sampled rows, bf16", st)
+    check_lowp(st)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_anim16_frames(precision):
     s = ni.make_scene("anim16_1024sq")
