@@ -172,6 +172,140 @@ def measured_traffic(kernel, precision):
         return None
 
 
+def _torus_trace_exact(o, v, step_scale, eps, far, budget=1024):
+    """Sphere tracing of the exact torus SDF (a true distance, so every step is
+    safe), float64, vectorised over rays: the reference surface of the fit."""
+    import numpy as np
+    import nnm_inputs as ni
+    o64, v64 = o.astype(np.float64), v.astype(np.float64)
+    tau = np.zeros(o.shape[0])
+    live = np.ones(o.shape[0], bool)
+    hit = np.zeros(o.shape[0], bool)
+    for _ in range(budget):
+        if not live.any():
+            break
+        d = ni.torus_sdf(o64[live] + tau[live, None] * v64[live])
+        tl = tau[live] + step_scale * d
+        tau[live] = tl
+        idx = np.flatnonzero(live)
+        done_hit = d <= eps
+        done_far = tl > far
+        hit[idx[done_hit & ~done_far]] = True
+        live[idx[done_hit | done_far]] = False
+    return hit, tau
+
+
+def _torus_normal(p):
+    import numpy as np
+    q = np.sqrt(p[:, 0] ** 2 + p[:, 1] ** 2)
+    g = np.stack([(q - 0.5) * p[:, 0] / q, (q - 0.5) * p[:, 1] / q, p[:, 2]], axis=1)
+    return g / np.linalg.norm(g, axis=1, keepdims=True)
+
+
+def run_fit_full():
+    """The whole fitting workload: 2000 Adam steps of the (256,2) SIREN on fresh
+    torus batches (host sampling prefetched on a thread pool), then fit quality
+    on a held-out batch and a 1080p FP32 render of the fitted net against an
+    exact sphere trace of the torus."""
+    import concurrent.futures as cf
+    import numpy as np
+    import torch
+    import nnm_inputs as ni
+    import paper_2201_09147_amd as nnm
+    scene = ni.make_scene("fit_torus_256x2")
+    ns, nu, steps, lr = scene.extra["n_surf"], scene.extra["n_unif"], scene.extra["steps"], scene.extra["lr"]
+    net = scene.levels[0].net
+    dev = torch.device("cuda", 0)
+    fit = nnm.Fit(net.d_in, net.width, net.n_sine, net.flat(), 0, ns + nu)
+    loss = torch.empty(4, dtype=torch.float32, device=dev)
+    ahead = 8
+    hist = []
+    with cf.ThreadPoolExecutor(4) as pool:
+        futs = {i: pool.submit(ni.torus_batch, i, ns, nu) for i in range(min(ahead, steps))}
+        t0 = time.perf_counter()
+        for i in range(steps):
+            b = futs.pop(i).result()
+            if i + ahead < steps:
+                futs[i + ahead] = pool.submit(ni.torus_batch, i + ahead, ns, nu)
+            fit.step_adam(*(torch.from_numpy(a).to(dev, non_blocking=False) for a in b), lr=lr, loss4=loss)
+            if i % 250 == 0 or i == steps - 1:
+                hist.append([i] + [round(float(x), 6) for x in loss.cpu().numpy()])
+                log(f"[fit-full] step {i}: loss terms {hist[-1][1:]}")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    params = fit.params()
+    fit.close()
+    # held-out quality
+    sx, sn, ux, us = ni.torus_batch(10 ** 6, ns, nu)
+    pt = torch.from_numpy(params).to(dev)
+    fs, gs = nnm.siren_forward_tangent(net.d_in, net.width, net.n_sine, pt, torch.from_numpy(sx).to(dev))
+    fu, gu = nnm.siren_forward_tangent(net.d_in, net.width, net.n_sine, pt, torch.from_numpy(ux).to(dev))
+    fs, gs, fu, gu = (a.cpu().numpy().astype(np.float64) for a in (fs, gs, fu, gu))
+    cosang = np.sum(gs * sn, axis=1) / np.maximum(np.linalg.norm(gs, axis=1), 1e-30)
+    quality = {"mean_abs_f_minus_sdf_uniform": float(np.mean(np.abs(fu - us))),
+               "mean_abs_f_surface": float(np.mean(np.abs(fs))),
+               "mean_normal_angle_deg_surface": float(np.degrees(np.mean(np.arccos(np.clip(cosang, -1, 1))))),
+               "mean_abs_gradnorm_minus_1_uniform": float(np.mean(np.abs(np.linalg.norm(gu, axis=1) - 1)))}
+    log(f"[fit-full] quality: {quality}")
+    # 1080p FP32 render of the fitted net (no Lipschitz bound: lipschitz_max = 0)
+    fitted = ni.Scene("fit_torus_256x2", [ni.SceneLevel(ni.SirenNet(net.d_in, net.width, net.n_sine,
+                                                                      ni.unflatten_params(params, net.d_in, net.width,
+                                                                                          net.n_sine)), 1.0)],
+                      1920, 1080, r0=0.0, base_sphere=False)
+    stack = nnm.load_siren_stack(fitted, "fp32", 0, lipschitz_max=0.0)
+    o_np, v_np, _ = fitted.rays()
+    # The net was fitted on [-1, 1]^3 only and is unconstrained outside, so the
+    # ray setup starts every ray at its entry into that box (slab test) and
+    # traces only the rays that enter it; depth adds the entry distance back,
+    # and hits beyond the ray's exit from the box count as misses.
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / v_np.astype(np.float64)
+        t1 = (-1.0 - o_np) * inv
+        t2 = (1.0 - o_np) * inv
+    t_in = np.maximum(np.max(np.minimum(t1, t2), axis=1), 0.0)
+    t_out = np.min(np.maximum(t1, t2), axis=1)
+    inbox = np.flatnonzero(t_out > t_in)
+    o_box = (o_np[inbox] + t_in[inbox, None] * v_np[inbox]).astype(np.float32)
+    o, v = torch.from_numpy(o_box).to(dev), torch.from_numpy(np.ascontiguousarray(v_np[inbox])).to(dev)
+    prm = nnm.TraceParams(fitted.step_scale, fitted.eps, fitted.far, fitted.max_steps)
+    out = nnm.render(stack, o, v, params=prm)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        out = nnm.render(stack, o, v, params=prm)
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    gb = {k: val.cpu().numpy() for k, val in out.items()}
+    n_all = o_np.shape[0]
+    g = {"hit": np.zeros(n_all, np.uint8), "depth": np.full(n_all, np.inf, np.float32),
+         "normal": np.zeros((n_all, 3), np.float32)}
+    # a hit past the ray's exit from the box is on the unconstrained part: a miss
+    inside = (gb["hit"] == 1) & (t_in[inbox] + gb["depth"] <= t_out[inbox])
+    g["hit"][inbox] = inside
+    g["depth"][inbox] = np.where(inside, t_in[inbox] + gb["depth"], np.inf).astype(np.float32)
+    g["normal"][inbox] = np.where(inside[:, None], gb["normal"], 0.0)
+    rows = np.arange(0, 1080, 8)
+    idx = (rows[:, None] * 1920 + np.arange(1920)[None, :]).reshape(-1)
+    rhit, rtau = _torus_trace_exact(o_np[idx], v_np[idx], fitted.step_scale, fitted.eps, fitted.far)
+    ghit = g["hit"][idx] == 1
+    both = ghit & rhit
+    p = o_np[idx][both].astype(np.float64) + g["depth"][idx][both, None] * v_np[idx][both].astype(np.float64)
+    na = np.degrees(np.arccos(np.clip(np.sum(g["normal"][idx][both] * _torus_normal(p), axis=1), -1, 1)))
+    render = {"ms_median": round(sorted(times)[2], 4), "rays_traced": int(inbox.size),
+              "hits": int(g["hit"].astype(np.int64).sum()),
+              "sample": f"every 8th row ({idx.size} rays) against an exact float64 sphere trace of the torus",
+              "mask_agreement_vs_exact": float(np.mean(ghit == rhit)),
+              "depth_abs_err_mean": float(np.mean(np.abs(g["depth"][idx][both] - rtau[both]))) if both.any() else None,
+              "depth_abs_err_max": float(np.max(np.abs(g["depth"][idx][both] - rtau[both]))) if both.any() else None,
+              "normal_angle_mean_deg_vs_exact": float(np.mean(na)) if both.any() else None}
+    log(f"[fit-full] render 1080p: {render}")
+    return {"steps": steps, "wall_s": round(wall, 2), "ms_per_step_incl_sampling": round(wall * 1e3 / steps, 3),
+            "loss_history": hist, "quality_held_out": quality, "render_1080p_fp32": render}
+
+
 def roofline(form):
     dom = max(form["kernels"], key=lambda k: k["avg_ms"])
     peak = PEAK_TFLOPS[form["precision"]]
@@ -192,6 +326,8 @@ def main():
     ap.add_argument("--cpu-rows-every", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fit-steps", type=int, default=10, help="fitting steps to time (0: skip)")
+    ap.add_argument("--fit-full", action="store_true",
+                    help="also run the whole 2000-step fit, its quality and a 1080p render of the fitted net")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -228,6 +364,8 @@ def main():
     results = {f: run_form(scene, f, o, v, t, args.steps, args.warmup) for f in forms}
 
     fit = run_fit(args.fit_steps, 2) if args.fit_steps > 0 else None
+    if fit is not None and args.fit_full:
+        fit["full"] = run_fit_full()
 
     cpu = None
     errors = {}

@@ -201,8 +201,10 @@ int siren_backward(const nnm_net_shape* shape, const float* params, int64_t n, c
 typedef struct nnm_fit nnm_fit;
 
 /* One batch of the eikonal fitting loss (device pointers):
-     L = mean_surf |N| + mean_surf (1 - n . grad N)
-       + mean_unif |N - sdf| + mean_unif (|grad N| - 1)^2  */
+     L = mean_surf |N| + mean_surf (1 - n . grad N / |grad N|)
+       + mean_unif |N - sdf| + mean_unif (|grad N| - 1)^2
+   (the normal term compares the unit gradient with n; it is 1 where
+   grad N = 0). */
 typedef struct {
   int64_t n_surf;
   int64_t n_unif;

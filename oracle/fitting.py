@@ -71,7 +71,10 @@ def net_value_grad(layers, x):
 def loss_terms(N_s, g_s, n_s, N_u, g_u, sdf_u):
     """The four loss terms (surface |N|, surface normal, uniform |N - sdf|, eikonal)."""
     t0 = np.mean(np.abs(N_s)) if N_s.size else 0.0
-    t1 = np.mean(1.0 - np.sum(n_s * g_s, axis=1)) if N_s.size else 0.0
+    # normal term on the unit gradient: 1 - n . grad N / |grad N| (cosine; 0 for a zero gradient)
+    gn = np.linalg.norm(g_s, axis=1)
+    cos = np.where(gn > 0.0, np.sum(n_s * g_s, axis=1) / np.where(gn > 0.0, gn, 1.0), 0.0)
+    t1 = np.mean(1.0 - cos) if N_s.size else 0.0
     t2 = np.mean(np.abs(N_u - sdf_u)) if N_u.size else 0.0
     t3 = np.mean((np.linalg.norm(g_u, axis=1) - 1.0) ** 2) if N_u.size else 0.0
     return np.array([t0, t1, t2, t3])
@@ -81,7 +84,13 @@ def loss_adjoints(N_s, g_s, n_s, N_u, g_u, sdf_u):
     """dL/dN and dL/dg per point, surface points first then uniform points."""
     ns, nu = N_s.shape[0], N_u.shape[0]
     Nb_s = np.sign(N_s) / max(ns, 1)
-    gb_s = -np.asarray(n_s, np.float64) / max(ns, 1)
+    # d/dg (1 - n . g / |g|) = -(n - (n . u) u) / |g| with u = g / |g|
+    n_s = np.asarray(n_s, np.float64)
+    gs_norm = np.linalg.norm(g_s, axis=1)
+    gs_safe = np.where(gs_norm > 0.0, gs_norm, 1.0)
+    u = g_s / gs_safe[:, None]
+    proj = n_s - np.sum(n_s * u, axis=1)[:, None] * u
+    gb_s = np.where(gs_norm[:, None] > 0.0, -proj / gs_safe[:, None], 0.0) / max(ns, 1)
     Nb_u = np.sign(N_u - sdf_u) / max(nu, 1)
     norm = np.linalg.norm(g_u, axis=1)
     safe = np.where(norm > 0.0, norm, 1.0)

@@ -167,12 +167,17 @@ __global__ void __launch_bounds__(kBlockThreads) k_fit_fb(FitArgs A) {
           const float* np_ = A.surf_n + 3LL * p;
           const float nx = np_[0], ny = np_[1], nz = np_[2];
           Nbar = (N > 0.f ? 1.f : (N < 0.f ? -1.f : 0.f)) * A.inv_ns;
-          gb[0] = -nx * A.inv_ns;
-          gb[1] = -ny * A.inv_ns;
-          gb[2] = -nz * A.inv_ns;
+          // normal term on the unit gradient, 1 - n . u with u = grad N / |grad N|:
+          // adjoint -(n - (n . u) u) / |grad N| (zero for a zero gradient)
+          const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
+          const float ig = gn > 0.f ? 1.f / gn : 0.f;
+          const float cs = (nx * gx + ny * gy + nz * gz) * ig;
+          gb[0] = -(nx - cs * gx * ig) * ig * A.inv_ns;
+          gb[1] = -(ny - cs * gy * ig) * ig * A.inv_ns;
+          gb[2] = -(nz - cs * gz * ig) * ig * A.inv_ns;
           if (c == 0 && g == 0) {
             lsum[0] += fabsf(N);
-            lsum[1] += 1.f - (nx * gx + ny * gy + nz * gz);
+            lsum[1] += 1.f - cs;
           }
         } else {
           const float sdf = A.unif_sdf[p - A.n_surf];

@@ -81,7 +81,8 @@ def test_p10_gradient_matches_torch_double_backward():
     (g,) = torch.autograd.grad(N.sum(), x, create_graph=True)
     n_s = torch.tensor(b[1])
     sdf = torch.tensor(b[3])
-    loss = (N[:ns].abs().mean() + (1 - (n_s * g[:ns]).sum(1)).mean() + (N[ns:] - sdf).abs().mean()
+    loss = (N[:ns].abs().mean() + (1 - (n_s * g[:ns]).sum(1) / g[:ns].norm(dim=1)).mean()
+            + (N[ns:] - sdf).abs().mean()
             + ((g[ns:].norm(dim=1) - 1) ** 2).mean())
     tg = torch.autograd.grad(loss, params)
     np.testing.assert_allclose(terms.sum(), loss.item(), rtol=1e-12)
