@@ -236,6 +236,7 @@ static double scene_value_grad(const orc_level* L, const orc_base_desc* B, const
 typedef struct {
   double step_scale, eps, far;
   int max_steps, final_level, normal_level;
+  const int* iters; /* NULL: eps-terminated; else evaluations per traced level (fixed-iteration mode) */
 } orc_trace_params;
 
 /* One ray of multiscale sphere tracing (Algorithm 1).  Readings:
@@ -246,6 +247,10 @@ typedef struct {
      max_steps evaluations; a non-finite d is a miss flagged NONFINITE;
    - d < 0 (a start inside the band, which Algorithm 1 excludes) is flagged;
    - depth is the ray parameter tau of the point after the last step.
+   Fixed-iteration mode (the paper's experiments fix the iteration counts): level
+   j takes exactly iters[j] steps, with no eps exit; tau > far is still a miss;
+   after the final traced level the ray is a hit when its last |d| <= eps, else
+   a miss flagged BUDGET.
    Optional log: tau before each step, d, level (up to log_cap events). */
 static int trace_one(const orc_level* lv, const orc_base_desc* B, const orc_trace_params* P,
                      const double o[3], const double v[3], double t, double* tau_out, uint8_t* steps,
@@ -275,6 +280,15 @@ static int trace_one(const orc_level* lv, const orc_base_desc* B, const orc_trac
         st |= ORC_ST_FAR;
         if (steps) steps[j] = (uint8_t)k;
         goto miss;
+      }
+      if (P->iters) {
+        if (k < P->iters[j]) continue;
+        if (j == P->final_level && fabs(d) > P->eps) {
+          st |= ORC_ST_BUDGET;
+          if (steps) steps[j] = (uint8_t)k;
+          goto miss;
+        }
+        break;
       }
       if (d <= P->eps) break;
       if (k >= P->max_steps) {
@@ -406,16 +420,19 @@ int orc_scene_eval(const orc_level_desc* level, const orc_base_desc* base, int64
    o, v: [n][3] float32 (v unit); t: [n] or NULL.
    Outputs: depth[n] (+inf on a miss), hit[n], normal[n][3] (0 on a miss; may be
    NULL), steps[n][m] (evaluations per level; may be NULL), status[n] (may be NULL). */
-int orc_trace(int m, const orc_level_desc* levels, const orc_base_desc* base, double step_scale, double eps,
-              double far, int max_steps, int final_level, int normal_level, int64_t n, const float* o,
-              const float* v, const float* t, double* depth, uint8_t* hit, double* normal, uint8_t* steps,
-              uint8_t* status, int threads) {
+int orc_trace_iters(int m, const orc_level_desc* levels, const orc_base_desc* base, double step_scale, double eps,
+                    double far, int max_steps, const int* iters, int final_level, int normal_level, int64_t n,
+                    const float* o, const float* v, const float* t, double* depth, uint8_t* hit, double* normal,
+                    uint8_t* steps, uint8_t* status, int threads) {
   if (m < 1 || m > ORC_MAX_LEVELS || final_level < 0 || final_level >= m || normal_level < 0 ||
       normal_level >= m || max_steps < 1 || max_steps > 255)
     return -1;
+  if (iters)
+    for (int j = 0; j <= final_level; ++j)
+      if (iters[j] < 1 || iters[j] > 255) return -1;
   orc_level lv[ORC_MAX_LEVELS];
   if (levels_load(lv, m, levels) != 0) return -1;
-  orc_trace_params P = {step_scale, eps, far, max_steps, final_level, normal_level};
+  orc_trace_params P = {step_scale, eps, far, max_steps, final_level, normal_level, iters};
   set_threads(threads);
   const size_t wsn = levels_ws(lv, m);
   int err = 0;
@@ -459,6 +476,15 @@ int orc_trace(int m, const orc_level_desc* levels, const orc_base_desc* base, do
   return err;
 }
 
+/* Eps-terminated multiscale sphere tracing (orc_trace_iters without iteration counts). */
+int orc_trace(int m, const orc_level_desc* levels, const orc_base_desc* base, double step_scale, double eps,
+              double far, int max_steps, int final_level, int normal_level, int64_t n, const float* o,
+              const float* v, const float* t, double* depth, uint8_t* hit, double* normal, uint8_t* steps,
+              uint8_t* status, int threads) {
+  return orc_trace_iters(m, levels, base, step_scale, eps, far, max_steps, NULL, final_level, normal_level, n, o, v,
+                         t, depth, hit, normal, steps, status, threads);
+}
+
 /* One ray with a log of every step: tau before the step, d, and the level.
    Returns the number of logged events (<= cap) and the status in *status. */
 int orc_trace_log(int m, const orc_level_desc* levels, const orc_base_desc* base, double step_scale, double eps,
@@ -467,7 +493,7 @@ int orc_trace_log(int m, const orc_level_desc* levels, const orc_base_desc* base
   if (m < 1 || m > ORC_MAX_LEVELS || final_level < 0 || final_level >= m) return -1;
   orc_level lv[ORC_MAX_LEVELS];
   if (levels_load(lv, m, levels) != 0) return -1;
-  orc_trace_params P = {step_scale, eps, far, max_steps, final_level, final_level};
+  orc_trace_params P = {step_scale, eps, far, max_steps, final_level, final_level, NULL};
   double* ws = (double*)malloc(levels_ws(lv, m) * sizeof(double));
   if (!ws) {
     levels_free(lv, m);

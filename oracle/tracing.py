@@ -40,11 +40,13 @@ def _load():
         lib.orc_scene_eval.argtypes = [P, P, c_int64, P, P, P, P, c_int]
         lib.orc_trace.argtypes = [c_int, P, P, c_double, c_double, c_double, c_int, c_int, c_int,
                                   c_int64, P, P, P, P, P, P, P, P, c_int]
+        lib.orc_trace_iters.argtypes = [c_int, P, P, c_double, c_double, c_double, c_int, P, c_int, c_int,
+                                        c_int64, P, P, P, P, P, P, P, P, c_int]
         lib.orc_trace_log.argtypes = [c_int, P, P, c_double, c_double, c_double, c_int, c_int, P, P,
                                       c_double, c_int, P, P, P, P, P]
         lib.orc_first_root.argtypes = [P, P, c_int64, P, P, P, c_double, c_double, c_double, c_double,
                                        P, c_int]
-        for f in (lib.orc_net_eval, lib.orc_scene_eval, lib.orc_trace, lib.orc_trace_log,
+        for f in (lib.orc_net_eval, lib.orc_scene_eval, lib.orc_trace, lib.orc_trace_iters, lib.orc_trace_log,
                   lib.orc_first_root):
             f.restype = c_int
         _lib = lib
@@ -118,9 +120,12 @@ def scene_eval(scene, level, x, t=None, grad=True, threads=0):
     return (val, g) if grad else val
 
 
-def trace(scene, o, v, t=None, final_level=None, normal_level=None, want_normal=True, threads=0):
+def trace(scene, o, v, t=None, final_level=None, normal_level=None, want_normal=True, threads=0,
+          iterations=None):
     """Multiscale sphere tracing of the rays (Algorithm 1) with normals.
 
+    ``iterations``: None for eps-terminated tracing, else the number of steps
+    of each traced level (fixed-iteration mode, as in the paper's experiments).
     Returns dict(depth, hit, normal, steps[n, m], status)."""
     m = len(scene.levels)
     final_level = m - 1 if final_level is None else final_level
@@ -136,10 +141,14 @@ def trace(scene, o, v, t=None, final_level=None, normal_level=None, want_normal=
     normal = np.empty((n, 3)) if want_normal else None
     steps = np.empty((n, m), np.uint8)
     status = np.empty(n, np.uint8)
-    rc = _load().orc_trace(m, lv.ptr(0), ctypes.cast(ctypes.byref(base), ctypes.c_void_p),
-                           scene.step_scale, scene.eps, scene.far, scene.max_steps, final_level,
-                           normal_level, n, _ptr(o), _ptr(v), _ptr(tt), _ptr(depth), _ptr(hit),
-                           _ptr(normal), _ptr(steps), _ptr(status), threads)
+    its = None
+    if iterations is not None:
+        its = np.zeros(8, np.int32)
+        its[:len(iterations)] = iterations
+    rc = _load().orc_trace_iters(m, lv.ptr(0), ctypes.cast(ctypes.byref(base), ctypes.c_void_p),
+                                 scene.step_scale, scene.eps, scene.far, scene.max_steps, _ptr(its),
+                                 final_level, normal_level, n, _ptr(o), _ptr(v), _ptr(tt), _ptr(depth),
+                                 _ptr(hit), _ptr(normal), _ptr(steps), _ptr(status), threads)
     if rc != 0:
         raise RuntimeError(f"orc_trace failed ({rc})")
     return {"depth": depth, "hit": hit, "normal": normal, "steps": steps, "status": status}

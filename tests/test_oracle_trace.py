@@ -255,3 +255,34 @@ def test_status_far_budget_and_start_inside():
     v = np.array([[0.0, 0.0, -1.0]], np.float32)
     r = T.trace(s, o, v)
     assert r["status"][0] & T.ST_NEG_STEP
+
+
+def test_fixed_iterations_sphere_recursion():
+    """Fixed-iteration mode on the analytic sphere (all amplitudes 0): every
+    level is the recursion tau <- tau + s (|o + tau v| - 0.6 - delta_j) taken
+    exactly iters[j] times (delta = 0 on the last traced level), a miss once
+    tau > far, and after the last level a hit iff the last |d| <= eps."""
+    s = ni.make_scene("stack3_512sq").with_size(48, 40).with_amplitudes([0.0, 0.0, 0.0])
+    o, v, _ = s.rays()
+    iters = [7, 4, 3]
+    for final in (2, 1):
+        r = T.trace(s, o, v, final_level=final, normal_level=final, iterations=iters)
+        o64, v64 = o.astype(np.float64), v.astype(np.float64)
+        tau = np.zeros(o.shape[0])
+        alive = np.ones(o.shape[0], bool)
+        last_d = np.zeros(o.shape[0])
+        for j in range(final + 1):
+            delta = 0.0 if j == final else s.levels[j].delta
+            for _ in range(iters[j]):
+                d = np.linalg.norm(o64 + tau[:, None] * v64, axis=1) - 0.6 - delta
+                tau = np.where(alive, tau + s.step_scale * d, tau)
+                last_d = np.where(alive, d, last_d)
+                alive &= tau <= s.far
+        hit = alive & (np.abs(last_d) <= s.eps)
+        assert np.array_equal(r["hit"] == 1, hit)
+        np.testing.assert_allclose(r["depth"][hit], tau[hit], rtol=0, atol=1e-12)
+        assert np.all(np.isinf(r["depth"][~hit]))
+        assert np.all(r["steps"][hit][:, :final + 1] == np.array(iters[:final + 1]))
+        # hits carry the sphere's radial normal
+        p = o64[hit] + tau[hit, None] * v64[hit]
+        np.testing.assert_allclose(r["normal"][hit], p / np.linalg.norm(p, axis=1, keepdims=True), atol=1e-12)
