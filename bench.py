@@ -306,6 +306,53 @@ def run_fit_full():
             "loss_history": hist, "quality_held_out": quality, "render_1080p_fp32": render}
 
 
+# The paper's Table 3 (RTX 3090, trained models, 512x512, precision not
+# stated): frames per second.  Context only, not a target.
+PAPER_TABLE3_FPS = {"table3_256x3": 19.8, "table3_64x1": 128.8, "table3_64x1_256x1": 73.1,
+                    "table3_64x1_256x2": 53.0, "table3_64x1_256x3": 41.6, "table3_64x1_256x1_256x3": 39.1}
+
+
+def run_table3(precisions, steps=20, warmup=3):
+    """The rows of Table 3 at 512x512 in fixed-iteration mode (20 steps on the
+    first net, 5 on the second in the last row; the last net of a nested row
+    gives the normals only), timed per call with HIP events."""
+    import torch
+    import nnm_inputs as ni
+    import paper_2201_09147_amd as nnm
+    dev = torch.device("cuda", 0)
+    rows = []
+    for name, (nets, iters, normal) in ni.TABLE3_ROWS.items():
+        scene = ni.make_scene(name)
+        o_np, v_np, _ = scene.rays()
+        o, v = torch.from_numpy(o_np).to(dev), torch.from_numpy(v_np).to(dev)
+        final = len(iters) - 1
+        row = {"scene": name, "nets": [f"({w},{k})" for w, k in nets], "iterations": iters,
+               "normal_net": normal, "paper_fps_rtx3090": PAPER_TABLE3_FPS[name]}
+        for prec in precisions:
+            stack = nnm.load_siren_stack(scene, prec, 0)
+            prm = nnm.TraceParams(scene.step_scale, scene.eps, scene.far, scene.max_steps, final, normal,
+                                  iterations=iters)
+            for _ in range(warmup):
+                out = nnm.render(stack, o, v, params=prm)
+            times = []
+            for _ in range(steps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                out = nnm.render(stack, o, v, params=prm)
+                b.record()
+                times.append((a, b))
+            torch.cuda.synchronize()
+            ms = sorted(a.elapsed_time(b) for a, b in times)[steps // 2]
+            row[prec] = {"ms_median": round(ms, 4), "fps": round(1e3 / ms, 1),
+                         "mrays_per_s": round(o_np.shape[0] / (ms * 1e-3) / 1e6, 1),
+                         "hits": int(out["hit"].to(torch.int64).sum().item())}
+            stack.close()
+        log(f"[table3] {name}: " + ", ".join(f"{p_} {row[p_]['fps']} FPS" for p_ in precisions)
+            + f" (paper, RTX 3090: {row['paper_fps_rtx3090']} FPS)")
+        rows.append(row)
+    return rows
+
+
 def roofline(form):
     dom = max(form["kernels"], key=lambda k: k["avg_ms"])
     peak = PEAK_TFLOPS[form["precision"]]
@@ -326,6 +373,8 @@ def main():
     ap.add_argument("--cpu-rows-every", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fit-steps", type=int, default=10, help="fitting steps to time (0: skip)")
+    ap.add_argument("--table3", action="store_true",
+                    help="also time the rows of the paper's Table 3 at 512^2 in fixed-iteration mode")
     ap.add_argument("--fit-full", action="store_true",
                     help="also run the whole 2000-step fit, its quality and a 1080p render of the fitted net")
     ap.add_argument("--copy-probe", action="store_true",
@@ -366,6 +415,7 @@ def main():
     fit = run_fit(args.fit_steps, 2) if args.fit_steps > 0 else None
     if fit is not None and args.fit_full:
         fit["full"] = run_fit_full()
+    table3 = run_table3([f for f in ("fp32", "bf16") if f in forms] or [args.precision]) if args.table3 else None
 
     cpu = None
     errors = {}
@@ -424,6 +474,7 @@ def main():
         "cpu_baseline": cpu,
         "errors_vs_oracle": errors,
         "fit": fit,
+        "table3_fixed_iterations": table3,
         "timing": head["timing"],
         "rays_per_s_median_call": round(n / (head["timing"]["median_ms"] * 1e-3), 1),
         "forms": {f: {"rays_per_s": round(r["rays_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),

@@ -91,7 +91,13 @@ typedef struct nnm_stack nnm_stack; /* opaque; immutable after loading */
 /* Multiscale sphere tracing parameters (Algorithm 1, Sec. 4).  Per level j the
    tracer repeats: d = f_j(o + tau v) - delta_j (delta = 0 on final_level);
    tau += step_scale * d; then tau > far -> miss; d <= eps -> next level;
-   max_steps evaluations used -> miss. */
+   max_steps evaluations used -> miss.
+   mode 1 is fixed-iteration tracing (the paper's experiments fix the iteration
+   counts, Sec. 6 and Table 3): level j <= final_level takes exactly
+   iterations[j] steps (1..255) with no eps exit; tau > far is still a miss;
+   after the final level a ray is a hit iff its last |d| <= eps (else a miss
+   flagged NNM_ST_BUDGET).  max_steps is unused in mode 1. */
+#define NNM_MAX_LEVELS 8
 typedef struct nnm_profiler nnm_profiler; /* see "profiling" below */
 
 typedef struct {
@@ -102,9 +108,10 @@ typedef struct {
   int32_t final_level;   /* last traced level (m - 1: full; m - 2: NNM) */
   int32_t normal_level;  /* level whose unit gradient is returned as the normal;
                             > final_level is neural normal mapping (Sec. 5) */
-  int32_t mode;          /* 0: eps-terminated (the only mode) */
+  int32_t mode;          /* 0: eps-terminated; 1: fixed iterations per level */
   int32_t reserved;
   nnm_profiler* profiler; /* NULL, or a profiler that times every kernel of the call */
+  int32_t iterations[NNM_MAX_LEVELS]; /* mode 1: steps of each traced level */
 } nnm_trace_params;
 
 /* ---------------------------------------------------------------- stacks */

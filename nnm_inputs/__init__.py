@@ -24,5 +24,5 @@ from .siren_init import (  # noqa: F401
 )
 from .camera import pinhole_rays  # noqa: F401
 from .torus import torus_sdf, torus_surface_samples, torus_uniform_samples, torus_batch  # noqa: F401
-from .scenes import SceneLevel, Scene, make_scene, WORKLOADS  # noqa: F401
+from .scenes import SceneLevel, Scene, make_scene, WORKLOADS, TABLE3_ROWS  # noqa: F401
 from .netfile import write_net_file, read_net_file  # noqa: F401

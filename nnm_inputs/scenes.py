@@ -16,6 +16,11 @@ Workloads (rays; levels as (width, k) in the paper's notation):
   anim16_1024sq       16 frames x 1024x1024, t = i/16; (64,1) s5 a=.005 on x - c(t)
                       |> 4-D (256,2) s4 a=.02, delta_1 = 0.05, rho = 0.2
   fit_torus_256x2     fitting a (256,2) net (seed 6) to the torus; rendered at 1080p
+  table3_*            the rows of the paper's Table 3 at 512x512, traced with fixed
+                      iteration counts (TABLE3_ROWS gives the counts and which net is
+                      used for neural normal mapping only): (64,1) s2 a=.015,
+                      (256,1) s21, (256,2) s3, (256,3) s23, a=.02 for the 256-wide nets,
+                      delta = (0.05, 0.01)
 """
 
 from dataclasses import dataclass, field
@@ -95,7 +100,31 @@ def _stack3():
     ]
 
 
+def _t3_net(shape):
+    if shape == (64, 1):
+        return SceneLevel(siren_init(2, 3, 64, 2, 0.015), 0.015, 0.05)
+    seed = {1: 21, 2: 3, 3: 23}[shape[1]]
+    return SceneLevel(siren_init(seed, 3, 256, shape[1] + 1, 0.02), 0.02, 0.0)
+
+
+# Table 3 rows: scene name -> (nets, iterations of the traced nets, normal net)
+TABLE3_ROWS = {
+    "table3_256x3": ([(256, 3)], [20], 0),
+    "table3_64x1": ([(64, 1)], [20], 0),
+    "table3_64x1_256x1": ([(64, 1), (256, 1)], [20], 1),
+    "table3_64x1_256x2": ([(64, 1), (256, 2)], [20], 1),
+    "table3_64x1_256x3": ([(64, 1), (256, 3)], [20], 1),
+    "table3_64x1_256x1_256x3": ([(64, 1), (256, 1), (256, 3)], [20, 5], 2),
+}
+
+
 def make_scene(name: str) -> Scene:
+    if name in TABLE3_ROWS:
+        nets = TABLE3_ROWS[name][0]
+        levels = [_t3_net(sh) for sh in nets]
+        if len(levels) == 3:
+            levels[1] = SceneLevel(levels[1].net, levels[1].amplitude, 0.01)
+        return Scene(name, levels, 512, 512)
     if name == "single_64x1_128sq":
         return Scene(name, [SceneLevel(siren_init(0, 3, 64, 2, 0.02), 0.02)], 128, 128)
     if name == "stack3_512sq":
@@ -119,4 +148,4 @@ def make_scene(name: str) -> Scene:
 
 
 WORKLOADS = ["single_64x1_128sq", "stack3_512sq", "stack3_1080p", "stack3_4096sq",
-             "anim16_1024sq", "fit_torus_256x2"]
+             "anim16_1024sq", "fit_torus_256x2"] + list(TABLE3_ROWS)

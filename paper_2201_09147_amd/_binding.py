@@ -4,7 +4,7 @@ import ctypes
 import os
 from ctypes import POINTER, c_double, c_float, c_int, c_int32, c_int64, c_void_p
 from dataclasses import dataclass
-from typing import List, Optional
+from typing import List, Optional, Sequence
 
 import numpy as np
 
@@ -37,7 +37,7 @@ class _StackDesc(ctypes.Structure):
 class _TraceParams(ctypes.Structure):
     _fields_ = [("step_scale", c_float), ("eps", c_float), ("far", c_float), ("max_steps", c_int32),
                 ("final_level", c_int32), ("normal_level", c_int32), ("mode", c_int32),
-                ("reserved", c_int32), ("profiler", c_void_p)]
+                ("reserved", c_int32), ("profiler", c_void_p), ("iterations", c_int32 * 8)]
 
 
 _PROF_MAX = 32
@@ -278,12 +278,19 @@ class TraceParams:
     normal_level: int = -1   # -1: final_level
     mode: int = 0
     profiler: Optional[Profiler] = None
+    iterations: Optional[Sequence[int]] = None  # fixed-iteration mode (mode 1): steps per traced level
 
     def c(self, m: int) -> _TraceParams:
         fl = m - 1 if self.final_level < 0 else self.final_level
         nl = fl if self.normal_level < 0 else self.normal_level
         prof = self.profiler.handle if self.profiler is not None else None
-        return _TraceParams(self.step_scale, self.eps, self.far, self.max_steps, fl, nl, self.mode, 0, prof)
+        mode = self.mode
+        its = (c_int32 * 8)()
+        if self.iterations is not None:
+            mode = 1
+            for j, k in enumerate(self.iterations):
+                its[j] = int(k)
+        return _TraceParams(self.step_scale, self.eps, self.far, self.max_steps, fl, nl, mode, 0, prof, its)
 
 
 def _dev_ptr(t, dtype, shape, name, device, allow_none=True):

@@ -516,7 +516,11 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
   if (!(p->eps > 0.f) || !std::isfinite(p->eps)) return fail(NNM_E_INVAL, "eps %g", p->eps);
   if (!(p->far > 0.f) || !std::isfinite(p->far)) return fail(NNM_E_INVAL, "far %g", p->far);
   if (p->max_steps < 1 || p->max_steps > 255) return fail(NNM_E_INVAL, "max_steps %d not in 1..255", p->max_steps);
-  if (p->mode != 0) return fail(NNM_E_UNSUPPORTED, "trace mode %d", p->mode);
+  if (p->mode != 0 && p->mode != 1) return fail(NNM_E_INVAL, "trace mode %d", p->mode);
+  if (p->mode == 1)
+    for (int j = 0; j <= p->final_level; ++j)
+      if (p->iterations[j] < 1 || p->iterations[j] > 255)
+        return fail(NNM_E_INVAL, "iterations[%d] = %d not in 1..255", j, p->iterations[j]);
   if (n == 0) return NNM_OK;
   if (!o || !v || !depth || !hit) return fail(NNM_E_INVAL, "null ray or output array");
   DeviceGuard guard(s->device);
@@ -570,6 +574,7 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
     a.step_scale = p->step_scale;
     a.eps = p->eps;
     a.far = p->far;
+    a.fixed_iters = p->mode == 1 ? p->iterations[j] : 0;
     a.delta = is_final ? 0.f : lv.delta;
     const bool ws_kernel = lv.dev.ws_ah && s->use_ws;
     ProfScope prof(p->profiler, 0, j, lv.width, ws_kernel ? 1 : 0, st);

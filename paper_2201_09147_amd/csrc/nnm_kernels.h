@@ -36,6 +36,7 @@ struct TraceLevelArgs {
   float eps;
   float far;
   float delta;  // delta of this level; 0 on the final level
+  int fixed_iters;  // > 0: fixed-iteration mode, exactly this many steps at this level
 };
 
 // Analytic normal of one level at the end points of the rays in a queue.

@@ -128,6 +128,17 @@ __global__ void __launch_bounds__(kBlockThreads) k_trace_level(TraceLevelArgs A)
         if (tau > A.far) {
           st |= ST_FAR;
           outcome = 2;
+        } else if (A.fixed_iters > 0) {
+          // fixed-iteration mode: leave the level after exactly fixed_iters steps;
+          // the final level hits iff its last |d| <= eps
+          if (k >= A.fixed_iters) {
+            if (A.is_final && fabsf(d) > A.eps) {
+              st |= ST_BUDGET;
+              outcome = 2;
+            } else {
+              outcome = 1;
+            }
+          }
         } else if (d <= A.eps) {
           outcome = 1;
         } else if (k >= A.max_steps) {

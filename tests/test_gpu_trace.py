@@ -91,6 +91,33 @@ def test_stack3_1080p_full_image_sampled_rows():
     del torch
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("mode", ["full", "nnm"])
+def test_fixed_iterations_match_oracle(precision, mode):
+    """Fixed-iteration mode (the paper's experiments): exact step counts per
+    level, hits decided by the last |d|, against the oracle's fixed mode."""
+    import torch
+    s = ni.make_scene("stack3_512sq").with_size(256, 200)
+    o, v, _ = s.rays()
+    final, normal = (2, 2) if mode == "full" else (1, 2)
+    its = [20, 10, 8][:final + 1]
+    stack = nnm.load_siren_stack(s, precision, 0)
+    dev = torch.device("cuda", 0)
+    p = nnm.TraceParams(s.step_scale, s.eps, s.far, s.max_steps, final, normal, iterations=its)
+    out = nnm.render(stack, torch.from_numpy(o).to(dev), torch.from_numpy(v).to(dev), None, p)
+    g = {k: val.cpu().numpy() for k, val in out.items()}
+    r = orc.trace(s, o, v, final_level=final, normal_level=normal, iterations=its)
+    st = compare(g, r)
+    _report(f"fixed iterations {its} {mode} {precision}", st)
+    (check_fp32 if precision == "fp32" else check_lowp)(st)
+    hit = g["hit"] == 1
+    assert np.all(g["steps"][hit][:, :final + 1] == np.array(its))
+    with pytest.raises(nnm.NnmError):
+        nnm.render(stack, torch.from_numpy(o[:4]).to(dev), torch.from_numpy(v[:4]).to(dev),
+                   params=nnm.TraceParams(iterations=[20, 0, 5]))
+    stack.close()
+
+
 def test_stack3_4096sq_stress_sampled_rows():
     """The 4096x4096 stress run (16.8 M rays) in one call, bf16; every 256th
     row checked against the oracle ray by ray, whole-frame invariants on all."""
