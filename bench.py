@@ -353,6 +353,36 @@ def run_table3(precisions, steps=20, warmup=3):
     return rows
 
 
+def run_nesting(workload, precision, n=100_000_000):
+    """Sampled sup |f_j - f_{j-1}| over [-1.5, 1.5]^3 for every adjacent pair of
+    the stack (nnm_sup_abs_diff, 1e8 points each) and the thresholds of
+    Proposition 1, beside the deltas the stack was built with."""
+    import torch
+    import nnm_inputs as ni
+    import paper_2201_09147_amd as nnm
+    scene = ni.make_scene(workload)
+    stack = nnm.load_siren_stack(scene, precision, 0)
+    pairs = []
+    for j in range(1, stack.m):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sup = nnm.nnm_sup_abs_diff(stack, j, j - 1, n, 1000 + j, -1.5, 1.5)
+        ms = (time.perf_counter() - t0) * 1e3
+        pairs.append({"levels": [j - 1, j], "sup_abs_diff": sup, "points": n, "ms": round(ms, 2),
+                      "points_per_s": round(n / (ms * 1e-3), 1)})
+        log(f"[nesting] sup |f{j} - f{j - 1}| over 1e8 points = {sup:.6f} ({ms:.1f} ms)")
+    eps = [p_["sup_abs_diff"] + 1e-4 for p_ in pairs]
+    deltas = [0.0] * stack.m
+    if stack.m > 1:
+        deltas[-1] = eps[-1]
+        for i in range(stack.m - 1, 0, -1):
+            deltas[i - 1] = deltas[i] + eps[i - 1]
+    stack.close()
+    return {"workload": workload, "precision": precision, "pairs": pairs,
+            "prop1_deltas": [round(d, 6) for d in deltas],
+            "configured_deltas": [lv.delta for lv in scene.levels[:-1]]}
+
+
 def roofline(form):
     dom = max(form["kernels"], key=lambda k: k["avg_ms"])
     peak = PEAK_TFLOPS[form["precision"]]
@@ -373,6 +403,8 @@ def main():
     ap.add_argument("--cpu-rows-every", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fit-steps", type=int, default=10, help="fitting steps to time (0: skip)")
+    ap.add_argument("--nesting", action="store_true",
+                    help="also estimate sup |f_j - f_(j-1)| of the stack over 1e8 points (Prop. 1 thresholds)")
     ap.add_argument("--table3", action="store_true",
                     help="also time the rows of the paper's Table 3 at 512^2 in fixed-iteration mode")
     ap.add_argument("--fit-full", action="store_true",
@@ -415,6 +447,7 @@ def main():
     fit = run_fit(args.fit_steps, 2) if args.fit_steps > 0 else None
     if fit is not None and args.fit_full:
         fit["full"] = run_fit_full()
+    nesting = run_nesting(args.workload, args.precision) if args.nesting else None
     table3 = run_table3([f for f in ("fp32", "bf16") if f in forms] or [args.precision]) if args.table3 else None
 
     cpu = None
@@ -475,6 +508,7 @@ def main():
         "errors_vs_oracle": errors,
         "fit": fit,
         "table3_fixed_iterations": table3,
+        "nesting": nesting,
         "timing": head["timing"],
         "rays_per_s_median_call": round(n / (head["timing"]["median_ms"] * 1e-3), 1),
         "forms": {f: {"rays_per_s": round(r["rays_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),

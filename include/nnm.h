@@ -252,6 +252,23 @@ int fit_write_state(nnm_fit* fit, const float* params, const float* adam_m, cons
 int64_t fit_get_step(const nnm_fit* fit);
 int fit_set_step(nnm_fit* fit, int64_t step);
 
+/* ------------------------------------------------------ nesting thresholds */
+
+/* Sampled infinity norm of f_a - f_b, the scene functions of two levels of a
+   stack, over the box [lo, hi]^3 (and t in [0, 1) when a level is 4-D or the
+   base moves): Sec. 4.2 approximates |f|_inf by a maximum over sampled
+   points, and Propositions 1-2 turn such bounds into nesting thresholds
+   (Prop. 1: delta_m = eps_m, delta_{i-1} = delta_i + eps_i with
+   eps_i > |f_i - f_{i-1}|_inf).  n points are drawn by splitmix64 from seed:
+   stream position k = 4 i + c for coordinate c of point i, u = (z >> 40) / 2^24,
+   x_c = float(lo + (hi - lo) u) evaluated in double, t = float(u) of c = 3.
+   out_max: one device float, overwritten (a NaN difference gives +inf).
+   Asynchronous on `stream`; allocates a stream-ordered scratch of about 24 MB.
+   Errors: NNM_E_INVAL (null, bad level, n < 1, empty box), NNM_E_NOMEM,
+   NNM_E_DEVICE. */
+int nnm_sup_abs_diff(const nnm_stack* s, int level_a, int level_b, int64_t n, uint64_t seed, float lo, float hi,
+                     float* out_max, void* stream);
+
 /* -------------------------------------------------------------- profiling */
 
 /* A profiler records a HIP event pair around every kernel that trace_rays

@@ -8,7 +8,7 @@ streams (default: the current stream).
 
 Entry points (same names as the C ABI in include/nnm.h):
   load_siren_stack, free_siren_stack, trace_rays, analytic_normal,
-  nnm_net_eval, nnm_validate_stack, nnm_read_net_file, nnm_sync
+  nnm_net_eval, nnm_sup_abs_diff, nnm_validate_stack, nnm_read_net_file, nnm_sync
 plus ``render`` (allocates outputs and calls trace_rays), the fitting entry
 points (``Fit`` over fit_create / fit_step, siren_forward_tangent,
 siren_backward) and ``paper_2201_09147_amd.autograd.SirenFn``.
@@ -33,6 +33,8 @@ from ._binding import (  # noqa: F401
     trace_rays,
     analytic_normal,
     nnm_net_eval,
+    nnm_sup_abs_diff,
+    nesting_thresholds,
     nnm_validate_stack,
     nnm_level_lipschitz_bound,
     nnm_read_net_file,

@@ -75,6 +75,7 @@ def load_library():
         "trace_rays": ([P, P, c_int64, P, P, P, P, P, P, P, P, P], c_int),
         "analytic_normal": ([P, c_int, c_int64, P, P, P, P, P], c_int),
         "nnm_net_eval": ([P, c_int, c_int64, P, P, P, P, P], c_int),
+        "nnm_sup_abs_diff": ([P, c_int, c_int, c_int64, ctypes.c_uint64, ctypes.c_float, ctypes.c_float, P, P], c_int),
         "nnm_read_net_file": ([ctypes.c_char_p, P, P, P, P, P], c_int),
         "nnm_free": ([P], None),
         "nnm_param_count": ([c_int32, c_int32, c_int32], c_int64),
@@ -359,6 +360,35 @@ def nnm_net_eval(stack: Stack, level: int, x, t, value, grad, stream=None):
         stack.handle, int(level), n, _dev_ptr(x, torch.float32, (n, 3), "x", dev, False),
         _dev_ptr(t, torch.float32, (n,), "t", dev), _dev_ptr(value, torch.float32, (n,), "value", dev),
         _dev_ptr(grad, torch.float32, (n, 3), "grad", dev), _stream_ptr(stream, dev)))
+
+
+def nnm_sup_abs_diff(stack: Stack, level_a: int, level_b: int, n: int, seed: int = 0, lo: float = -1.5,
+                     hi: float = 1.5, out=None, stream=None) -> float:
+    """Sampled sup |f_a - f_b| over [lo, hi]^3 (nnm_sup_abs_diff); returns it as a float."""
+    import torch
+    dev = torch.device("cuda", stack.device)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float32, device=dev)
+    _check(load_library().nnm_sup_abs_diff(stack.handle, int(level_a), int(level_b), ctypes.c_int64(int(n)),
+                                           ctypes.c_uint64(int(seed)), ctypes.c_float(lo), ctypes.c_float(hi),
+                                           _dev_ptr(out, torch.float32, (1,), "out", stack.device, False),
+                                           _stream_ptr(stream, stack.device)))
+    return float(out.item())
+
+
+def nesting_thresholds(stack: Stack, n: int = 1 << 24, seed: int = 0, lo: float = -1.5, hi: float = 1.5,
+                       margin: float = 1e-4):
+    """Thresholds by Proposition 1 from sampled bounds eps_i = sup |f_i - f_{i-1}| + margin
+    (i = 1 .. m-1, zero-based): delta_{m-1} = eps_{m-1}, delta_{i-1} = delta_i + eps_i.
+    Returns (deltas[m], eps[m-1])."""
+    m = stack.m
+    eps = [nnm_sup_abs_diff(stack, i, i - 1, n, seed + i, lo, hi) + margin for i in range(1, m)]
+    deltas = [0.0] * m
+    if m > 1:
+        deltas[m - 1] = eps[m - 2]
+        for i in range(m - 1, 0, -1):
+            deltas[i - 1] = deltas[i] + eps[i - 1]
+    return deltas, eps
 
 
 def nnm_sync(stream=None, device: int = 0):

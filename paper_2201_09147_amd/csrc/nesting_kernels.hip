@@ -1,0 +1,66 @@
+// nesting_kernels.hip -- sampled sup |f_a - f_b| over a box, the quantity the
+// paper's Propositions 1-2 turn into nesting thresholds (Sec. 4.2: the infinity
+// norm on the training domain, approximated by a maximum over sampled points).
+//
+// Points come from a counter-based generator so that any other implementation
+// can reproduce them exactly: splitmix64 (Steele, Lea and Flood, 2014, with
+// Vigna's published finaliser), stream position k = 4 i + c for coordinate c of
+// point i, u = top 24 bits / 2^24, x_c = float(lo + (hi - lo) u) evaluated in
+// double (one rounding), and the time coordinate t = u of c = 3.
+#include "nnm_kernels.h"
+
+namespace nnm {
+
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_box_points(uint64_t seed, long long base, int count, float lo, float hi, float* x, float* t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint64_t p = (uint64_t)(base + i);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double u = (double)(splitmix64_at(seed, 4ull * p + c) >> 40) * (1.0 / 16777216.0);
+    x[3 * i + c] = (float)((double)lo + ((double)hi - (double)lo) * u);
+  }
+  if (t) t[i] = (float)((double)(splitmix64_at(seed, 4ull * p + 3) >> 40) * (1.0 / 16777216.0));
+}
+
+// Non-negative floats order like their bit patterns, so the maximum is an
+// unsigned atomicMax; a NaN difference counts as +inf.
+__global__ void k_absdiff_max(const float* fa, const float* fb, int count, unsigned int* out) {
+  __shared__ float red[256];
+  float m = 0.f;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    float d = fabsf(fa[i] - fb[i]);
+    if (!(d >= 0.f)) d = __builtin_inff();
+    m = fmaxf(m, d);
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
+}
+
+hipError_t launch_box_points(uint64_t seed, long long base, int count, float lo, float hi, float* x, float* t,
+                             hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_box_points, dim3((count + 255) / 256), dim3(256), 0, s, seed, base, count, lo, hi, x, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_absdiff_max(const float* fa, const float* fb, int count, unsigned int* out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int grid = std::min(2048, (count + 255) / 256);
+  hipLaunchKernelGGL(k_absdiff_max, dim3(grid), dim3(256), 0, s, fa, fb, count, out);
+  return hipGetLastError();
+}
+
+}  // namespace nnm

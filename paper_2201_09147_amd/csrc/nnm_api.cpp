@@ -658,6 +658,47 @@ int nnm_net_eval(const nnm_stack* s, int level, int64_t n, const float* x, const
   return points_common(s, level, n, x, t, value, grad, stream, 1);
 }
 
+int nnm_sup_abs_diff(const nnm_stack* s, int level_a, int level_b, int64_t n, uint64_t seed, float lo, float hi,
+                     float* out_max, void* stream) {
+  g_err.clear();
+  if (!s || !out_max) return fail(NNM_E_INVAL, "null stack or output");
+  if (level_a < 0 || level_a >= s->m || level_b < 0 || level_b >= s->m)
+    return fail(NNM_E_INVAL, "levels %d, %d of %d", level_a, level_b, s->m);
+  if (n < 1) return fail(NNM_E_INVAL, "n = %lld < 1", (long long)n);
+  if (!(lo < hi) || !std::isfinite(lo) || !std::isfinite(hi)) return fail(NNM_E_INVAL, "box [%g, %g]", lo, hi);
+  DeviceGuard guard(s->device);
+  if (!guard.ok) return fail(NNM_E_DEVICE, "hipSetDevice(%d) failed", s->device);
+  hipStream_t st = (hipStream_t)stream;
+  // time-conditioned nets or a moving base: the time is sampled too
+  const bool with_t = s->levels[level_a].d_in == 4 || s->levels[level_b].d_in == 4 || s->base.rho != 0.f;
+  const int chunk = (int)std::min<int64_t>(n, 1 << 22);
+  const size_t off_x = 0, off_t = align256((size_t)chunk * 12), off_a = off_t + align256((size_t)chunk * 4),
+               off_b = off_a + align256((size_t)chunk * 4);
+  const size_t total = off_b + align256((size_t)chunk * 4);
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, total, st);
+  if (e != hipSuccess) return fail(NNM_E_NOMEM, "hipMallocAsync(%zu): %s", total, hipGetErrorString(e));
+  char* wb = (char*)ws;
+  float* x = (float*)(wb + off_x);
+  float* t = with_t ? (float*)(wb + off_t) : nullptr;
+  float* fa = (float*)(wb + off_a);
+  float* fb = (float*)(wb + off_b);
+  int rc = NNM_OK;
+  if ((e = launch_zero_ints((int*)out_max, 1, st)) != hipSuccess) rc = hip_fail(e, "zeroing the maximum");
+  for (int64_t base = 0; base < n && rc == NNM_OK; base += chunk) {
+    const int cnt = (int)std::min<int64_t>(chunk, n - base);
+    if ((e = launch_box_points(seed, base, cnt, lo, hi, x, t, st)) != hipSuccess) {
+      rc = hip_fail(e, "sampling points");
+      break;
+    }
+    if ((rc = points_common(s, level_a, cnt, x, t, fa, nullptr, stream, 0)) != NNM_OK) break;
+    if ((rc = points_common(s, level_b, cnt, x, t, fb, nullptr, stream, 0)) != NNM_OK) break;
+    if ((e = launch_absdiff_max(fa, fb, cnt, (unsigned int*)out_max, st)) != hipSuccess) rc = hip_fail(e, "max reduction");
+  }
+  if ((e = hipFreeAsync(ws, st)) != hipSuccess && rc == NNM_OK) rc = hip_fail(e, "hipFreeAsync");
+  return rc;
+}
+
 int nnm_profiler_create(nnm_profiler** out) {
   if (!out) return fail(NNM_E_INVAL, "null output handle");
   *out = new nnm_profiler();

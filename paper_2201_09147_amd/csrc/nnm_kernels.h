@@ -134,6 +134,9 @@ hipError_t launch_wgrad(int H, const float* abar, const float* X, long long Kc, 
 hipError_t launch_masked_sum(const float* a, const float* m, long long n, float* out, hipStream_t s);
 
 hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
+hipError_t launch_box_points(uint64_t seed, long long base, int count, float lo, float hi, float* x, float* t,
+                             hipStream_t s);
+hipError_t launch_absdiff_max(const float* fa, const float* fb, int count, unsigned int* out, hipStream_t s);
 hipError_t launch_trace_level(int width, int prec, const TraceLevelArgs& a, int grid, hipStream_t s);
 hipError_t launch_normal(int width, int prec, const NormalArgs& a, int grid, hipStream_t s);
 hipError_t launch_points(int width, int prec, const PointsArgs& a, int grid, hipStream_t s);

@@ -108,3 +108,33 @@ def test_empty_and_single_point():
     assert abs(v.item() - rv[0]) <= 1e-5 * max(1, abs(rv[0]))
     np.testing.assert_allclose(g.cpu().numpy()[0], rg[0], atol=1e-5 * np.abs(rg).max())
     stack.close()
+
+
+@pytest.mark.parametrize("name,precision,pairs", [
+    ("stack3_512sq", "fp32", [(1, 0), (2, 1)]),
+    ("stack3_512sq", "bf16", [(2, 1)]),
+    ("anim16_1024sq", "fp32", [(1, 0)]),
+])
+def test_sup_abs_diff_matches_oracle_on_the_same_points(name, precision, pairs):
+    """nnm_sup_abs_diff (sampled |f_a - f_b|_inf, Sec. 4.2) against the oracle's
+    float64 maximum over exactly the points the device drew (splitmix64)."""
+    import torch
+    import paper_2201_09147_amd as nnm
+    from nnm_inputs.sampling import box_points
+    s = ni.make_scene(name)
+    stack = nnm.load_siren_stack(s, precision, 0)
+    n, seed, lo, hi = (1 << 16) + 77, 1234, -1.5, 1.5
+    x, t = box_points(seed, n, lo, hi)
+    timed = s.frames > 1 or any(l.net.d_in == 4 for l in s.levels)
+    for a, b in pairs:
+        got = nnm.nnm_sup_abs_diff(stack, a, b, n, seed, lo, hi)
+        fa = orc.scene_eval(s, a, x, t if timed else None, grad=False)
+        fb = orc.scene_eval(s, b, x, t if timed else None, grad=False)
+        ref = float(np.max(np.abs(fa - fb)))
+        tol = 2e-6 + 1e-4 * ref if precision == "fp32" else 3e-2 * ref
+        print(f"{name} {precision} sup|f{a} - f{b}| gpu {got:.6e} oracle {ref:.6e}")
+        assert abs(got - ref) <= tol
+    deltas, eps = nnm.nesting_thresholds(stack, n=n, seed=seed)
+    assert all(d > 0 for d in deltas) and all(deltas[i] > deltas[i + 1] for i in range(len(deltas) - 1))
+    stack.close()
+    del torch
