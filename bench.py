@@ -383,6 +383,126 @@ def run_nesting(workload, precision, n=100_000_000):
             "configured_deltas": [lv.delta for lv in scene.levels[:-1]]}
 
 
+def _clip_to_box(o_np, v_np):
+    """Entry and exit parameters of each ray with the box [-1, 1]^3 (slab test)."""
+    import numpy as np
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / v_np.astype(np.float64)
+        t1 = (-1.0 - o_np) * inv
+        t2 = (1.0 - o_np) * inv
+    t_in = np.maximum(np.max(np.minimum(t1, t2), axis=1), 0.0)
+    t_out = np.min(np.maximum(t1, t2), axis=1)
+    return t_in, t_out
+
+
+def run_capacity(steps=2000):
+    """Capacity-sequence training (Sec. 4.2): the three shapes of the nested
+    stack, (32,1), (64,1) and (256,2), fitted to the torus on the same batches;
+    nesting thresholds from the sampled sup |f_j - f_(j-1)| by Proposition 1;
+    then multiscale sphere tracing of the trained stack at 1080p against single-
+    level tracing of the finest net and against the exact torus."""
+    import concurrent.futures as cf
+    import numpy as np
+    import torch
+    import nnm_inputs as ni
+    import paper_2201_09147_amd as nnm
+    scene = ni.make_scene("fit_torus_256x2")
+    ns, nu, lr = scene.extra["n_surf"], scene.extra["n_unif"], scene.extra["lr"]
+    dev = torch.device("cuda", 0)
+    # width, sine layers, init seed, Adam lr (the small nets learn slowly at 1e-4)
+    shapes = [(32, 2, 11, 1e-3), (64, 2, 12, 1e-3), (256, 3, 6, lr)]
+    nets = [ni.siren_init(seed, 3, w, k, 1.0, normalise=False) for w, k, seed, _ in shapes]
+    fits = [nnm.Fit(3, n_.width, n_.n_sine, n_.flat(), 0, ns + nu) for n_ in nets]
+    losses = [torch.empty(4, dtype=torch.float32, device=dev) for _ in nets]
+    ahead = 8
+    with cf.ThreadPoolExecutor(4) as pool:
+        futs = {i: pool.submit(ni.torus_batch, i, ns, nu) for i in range(min(ahead, steps))}
+        t0 = time.perf_counter()
+        for i in range(steps):
+            b = futs.pop(i).result()
+            if i + ahead < steps:
+                futs[i + ahead] = pool.submit(ni.torus_batch, i + ahead, ns, nu)
+            bt = tuple(torch.from_numpy(a).to(dev) for a in b)
+            for f, l, sh in zip(fits, losses, shapes):
+                f.step_adam(*bt, lr=sh[3], loss4=l)
+            if i % 500 == 0 or i == steps - 1:
+                log(f"[capacity] step {i}: " + " | ".join(
+                    f"({n_.width},{n_.n_sine - 1}) {sum(l.cpu().tolist()):.4f}" for n_, l in zip(nets, losses)))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    fitted = [ni.SirenNet(3, n_.width, n_.n_sine, ni.unflatten_params(f.params(), 3, n_.width, n_.n_sine))
+              for n_, f in zip(nets, fits)]
+    final_loss = [[round(float(x), 6) for x in l.cpu().numpy()] for l in losses]
+    for f in fits:
+        f.close()
+
+    def make(levels, deltas):
+        lv = [ni.SceneLevel(n_, 1.0, d) for n_, d in zip(levels, deltas)]
+        return ni.Scene("capacity_torus", lv, 1920, 1080, r0=0.0, base_sphere=False)
+
+    # thresholds by Proposition 1 on the training domain
+    probe = nnm.load_siren_stack(make(fitted, [1.0, 0.5, 0.0]), "fp32", 0, lipschitz_max=0.0)
+    sups = [nnm.nnm_sup_abs_diff(probe, j, j - 1, 1 << 26, 77 + j, -1.0, 1.0) for j in (1, 2)]
+    probe.close()
+    # Prop. 1 (zero-based): eps_j > sup |f_j - f_(j-1)|; delta_2 = eps_2,
+    # delta_1 = delta_2 + eps_2, delta_0 = delta_1 + eps_1 (delta_2 is the fine
+    # net's band, unused: the last level is traced to its zero set)
+    margin = 1e-3
+    eps = [sups[0] + margin, sups[1] + margin]
+    deltas = [2 * eps[1] + eps[0], 2 * eps[1]]
+    log(f"[capacity] sup |f1 - f0| = {sups[0]:.5f}, sup |f2 - f1| = {sups[1]:.5f}; deltas {deltas}")
+    o_np, v_np, _ = make(fitted, deltas + [0.0]).rays()
+    t_in, t_out = _clip_to_box(o_np, v_np)
+    inbox = np.flatnonzero(t_out > t_in)
+    o = torch.from_numpy((o_np[inbox] + t_in[inbox, None] * v_np[inbox]).astype(np.float32)).to(dev)
+    v = torch.from_numpy(np.ascontiguousarray(v_np[inbox])).to(dev)
+    rows = np.arange(0, 1080, 8)
+    idx = (rows[:, None] * 1920 + np.arange(1920)[None, :]).reshape(-1)
+    rhit, rtau = _torus_trace_exact(o_np[idx], v_np[idx], scene.step_scale, scene.eps, scene.far)
+    out_rows = {}
+    for label, sc in (("multiscale 3-level", make(fitted, deltas + [0.0])), ("single (256,2)", make(fitted[2:], [0.0]))):
+        for prec in ("fp32", "bf16"):
+            stack = nnm.load_siren_stack(sc, prec, 0, lipschitz_max=0.0)
+            prm = nnm.TraceParams(sc.step_scale, sc.eps, sc.far, sc.max_steps)
+            out = nnm.render(stack, o, v, params=prm)
+            times = []
+            for _ in range(7):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                out = nnm.render(stack, o, v, params=prm)
+                b.record()
+                times.append((a, b))
+            torch.cuda.synchronize()
+            ms = sorted(a.elapsed_time(b) for a, b in times)[3]
+            gb = {k: val.cpu().numpy() for k, val in out.items()}
+            stack.close()
+            hit = np.zeros(o_np.shape[0], bool)
+            depth = np.full(o_np.shape[0], np.inf)
+            ins = (gb["hit"] == 1) & (t_in[inbox] + gb["depth"] <= t_out[inbox])
+            hit[inbox] = ins
+            depth[inbox] = np.where(ins, t_in[inbox] + gb["depth"], np.inf)
+            both = hit[idx] & rhit
+            out_rows[f"{label} {prec}"] = {
+                "ms_median": round(ms, 4), "rays_traced": int(inbox.size), "hits": int(hit.sum()),
+                "mask_agreement_vs_exact_torus": float(np.mean(hit[idx] == rhit)),
+                "depth_abs_err_mean_vs_exact": float(np.mean(np.abs(depth[idx][both] - rtau[both]))),
+                "evals_per_level": gb["steps"].astype(np.int64).sum(axis=0).tolist(), "_depth": depth, "_hit": hit}
+            log(f"[capacity] {label} {prec}: {ms:.3f} ms, hits {int(hit.sum())}, mask agreement vs exact "
+                f"{out_rows[f'{label} {prec}']['mask_agreement_vs_exact_torus']:.5f}")
+    for prec in ("fp32", "bf16"):
+        a, b = out_rows[f"multiscale 3-level {prec}"], out_rows[f"single (256,2) {prec}"]
+        both = a["_hit"] & b["_hit"]
+        a["vs_single_level"] = {"mask_agreement": float(np.mean(a["_hit"] == b["_hit"])),
+                                "depth_max_abs_diff": float(np.max(np.abs(a["_depth"][both] - b["_depth"][both]))),
+                                "speedup": round(b["ms_median"] / a["ms_median"], 3)}
+    for r in out_rows.values():
+        r.pop("_depth")
+        r.pop("_hit")
+    return {"steps": steps, "wall_s": round(wall, 2), "nets": ["(32,1)", "(64,1)", "(256,2)"],
+            "adam_lr": [sh[3] for sh in shapes],
+            "final_loss4": final_loss, "sup_abs_diff": sups, "deltas_prop1": deltas, "renders_1080p": out_rows}
+
+
 def roofline(form):
     dom = max(form["kernels"], key=lambda k: k["avg_ms"])
     peak = PEAK_TFLOPS[form["precision"]]
@@ -403,6 +523,8 @@ def main():
     ap.add_argument("--cpu-rows-every", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fit-steps", type=int, default=10, help="fitting steps to time (0: skip)")
+    ap.add_argument("--capacity", action="store_true",
+                    help="also fit (32,1), (64,1), (256,2) to the torus, nest them by Prop. 1 and render at 1080p")
     ap.add_argument("--nesting", action="store_true",
                     help="also estimate sup |f_j - f_(j-1)| of the stack over 1e8 points (Prop. 1 thresholds)")
     ap.add_argument("--table3", action="store_true",
@@ -448,6 +570,7 @@ def main():
     if fit is not None and args.fit_full:
         fit["full"] = run_fit_full()
     nesting = run_nesting(args.workload, args.precision) if args.nesting else None
+    capacity = run_capacity() if args.capacity else None
     table3 = run_table3([f for f in ("fp32", "bf16") if f in forms] or [args.precision]) if args.table3 else None
 
     cpu = None
@@ -509,6 +632,7 @@ def main():
         "fit": fit,
         "table3_fixed_iterations": table3,
         "nesting": nesting,
+        "capacity_sequence": capacity,
         "timing": head["timing"],
         "rays_per_s_median_call": round(n / (head["timing"]["median_ms"] * 1e-3), 1),
         "forms": {f: {"rays_per_s": round(r["rays_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
