@@ -8,7 +8,8 @@ tracing, no network evaluation, no normals).  It only produces inputs:
   Lipschitz-safe by scaling the output layer;
 * pinhole-camera rays;
 * the torus training data for the fitting workload;
-* the scene descriptions of the five standard workloads.
+* the scene descriptions of the five standard workloads;
+* regular grids of sample points.
 
 All randomness comes from numpy's PCG64 (`numpy.random.default_rng`) and all
 derived values are computed in float64 before being rounded once to float32.
@@ -26,3 +27,4 @@ from .camera import pinhole_rays  # noqa: F401
 from .torus import torus_sdf, torus_surface_samples, torus_uniform_samples, torus_batch  # noqa: F401
 from .scenes import SceneLevel, Scene, make_scene, WORKLOADS, TABLE3_ROWS  # noqa: F401
 from .netfile import write_net_file, read_net_file  # noqa: F401
+from .grid import grid_axis, grid_nodes  # noqa: F401

@@ -4,7 +4,7 @@ import os
 import subprocess
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "nnm_oracle.c")
+_SRCS = [os.path.join(_HERE, "nnm_oracle.c"), os.path.join(_HERE, "mesh_oracle.c")]
 _LIB = os.path.join(_HERE, "libnnm_oracle.so")
 
 
@@ -13,12 +13,12 @@ def oracle_lib_path() -> str:
 
 
 def build_oracle(force: bool = True) -> str:
-    """Compile ``nnm_oracle.c`` into ``libnnm_oracle.so`` (always, when force)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+    """Compile the oracle sources into ``libnnm_oracle.so`` (always, when force)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= max(os.path.getmtime(s) for s in _SRCS):
         return _LIB
     tmp = _LIB + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fopenmp", "-fPIC", "-shared",
-           "-o", tmp, _SRC, "-lm"]
+           "-o", tmp, *_SRCS, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
     return _LIB
