@@ -383,6 +383,99 @@ def run_nesting(workload, precision, n=100_000_000):
             "configured_deltas": [lv.delta for lv in scene.levels[:-1]]}
 
 
+def run_mesh(workload, precision, res=512, steps=10, warmup=2):
+    """Neural normal mapping onto a triangle mesh (Sec. 5, Fig. 5): the coarse
+    (64,1) level on a res^3 grid (nnm_grid_values), its marching-tetrahedra
+    mesh (nnm_mesh_extract), and the fine level's normals at the vertices
+    (neural_normal_map).  Each stage is timed with HIP events on the stream the
+    kernels run on.  Quality: normals of the coarse level (the mesh's own
+    surface) and the mapped fine normals, both against the fine level's normal
+    at the vertex projected onto the fine surface (two Newton steps along the
+    gradient), as mean angle and mean squared difference of unit normals."""
+    import numpy as np
+    import torch
+    import nnm_inputs as ni
+    import paper_2201_09147_amd as nnm
+    scene = ni.make_scene(workload)
+    coarse, fine = len(scene.levels) - 2, len(scene.levels) - 1
+    stack = nnm.load_siren_stack(scene, precision, 0)
+    dev = torch.device("cuda", 0)
+    lo, hi = -1.0, 1.0
+    vals = torch.empty((res, res, res), dtype=torch.float32, device=dev)
+    nnm.nnm_grid_values(stack, coarse, res, lo, hi, values=vals)
+    V, T = nnm.extract_mesh(vals, lo, hi)
+    nv, nt = int(V.shape[0]), int(T.shape[0])
+    verts = torch.empty((nv, 3), dtype=torch.float32, device=dev)
+    tris = torch.empty((nt, 3), dtype=torch.int32, device=dev)
+    counts = torch.empty(2, dtype=torch.int64, device=dev)
+    normals = torch.empty((nv, 3), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        ms = []
+        for _ in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    ms_grid = timed(lambda: nnm.nnm_grid_values(stack, coarse, res, lo, hi, values=vals))
+    ms_ext = timed(lambda: nnm.nnm_mesh_extract(vals, lo, hi, 0.0, verts, tris, counts))
+    ms_nrm = timed(lambda: nnm.neural_normal_map(stack, fine, verts, normal=normals))
+    ms_all = timed(lambda: (nnm.nnm_grid_values(stack, coarse, res, lo, hi, values=vals),
+                            nnm.nnm_mesh_extract(vals, lo, hi, 0.0, verts, tris, counts),
+                            nnm.neural_normal_map(stack, fine, verts, normal=normals)))
+    torch.cuda.synchronize()
+    assert counts.cpu().tolist() == [nv, nt]
+    # quality against the fine surface
+    coarse_n = nnm.neural_normal_map(stack, coarse, verts)
+    x = verts.clone()
+    val = torch.empty(nv, dtype=torch.float32, device=dev)
+    grad = torch.empty((nv, 3), dtype=torch.float32, device=dev)
+    for _ in range(2):
+        nnm.analytic_normal(stack, fine, x, None, val, grad)
+        x = x - (val / grad.square().sum(1).clamp_min(1e-12))[:, None] * grad
+    ref_n = nnm.neural_normal_map(stack, fine, x)
+    nnm.analytic_normal(stack, fine, x, None, val, grad)
+    torch.cuda.synchronize()
+
+    def stats(a):
+        cosv = (a * ref_n).sum(1).clamp(-1, 1)
+        ang = torch.rad2deg(torch.acos(cosv))
+        return {"angle_mean_deg": round(float(ang.mean()), 4), "angle_p99_deg": round(float(ang.quantile(0.99)), 4)
+                if nv <= 1 << 24 else None, "mse": float((a - ref_n).square().sum(1).mean())}
+
+    q_coarse, q_nnm = stats(coarse_n), stats(normals)
+    hflops = normal_hidden_flops(scene.levels[fine].net)
+    tflops = hflops * nv / (ms_nrm * 1e-3) / 1e12
+    peak = 2500.0 if precision in ("bf16", "fp16") else 157.3
+    ext_bytes = 4 * res ** 3 + 12 * nv + 12 * nt
+    out = {"workload": f"{workload} levels {coarse} -> {fine}", "precision": precision, "grid": res,
+           "vertices": nv, "triangles": nt,
+           "ms": {"grid_values": round(ms_grid, 4), "extract": round(ms_ext, 4), "neural_normal_map": round(ms_nrm, 4),
+                  "all": round(ms_all, 4)},
+           "grid_nodes_per_s": round(res ** 3 / (ms_grid * 1e-3), 1),
+           "mapped_vertices_per_s": round(nv / (ms_nrm * 1e-3), 1),
+           "normal_roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": peak, "unit": "TFLOP/s",
+                               "frac": round(tflops / peak, 4)},
+           "extract_roofline": {"bound": "hbm", "achieved": round(ext_bytes / (ms_ext * 1e-3) / 1e9, 1),
+                                "peak": 8000.0, "unit": "GB/s",
+                                "frac": round(ext_bytes / (ms_ext * 1e-3) / 8e12, 4)},
+           "fine_surface_residual_max": float(val.abs().max()),
+           "quality_vs_fine_surface": {"coarse_normals": q_coarse, "mapped_normals": q_nnm}}
+    log(f"[mesh {precision}] {res}^3 grid {ms_grid:.3f} ms, extract {ms_ext:.3f} ms ({nv} verts, {nt} tris), "
+        f"normals {ms_nrm:.3f} ms ({tflops:.1f} TFLOP/s), all {ms_all:.3f} ms; normals vs the fine surface: "
+        f"coarse {q_coarse['angle_mean_deg']:.4f} deg (MSE {q_coarse['mse']:.3e}), mapped "
+        f"{q_nnm['angle_mean_deg']:.4f} deg (MSE {q_nnm['mse']:.3e})")
+    stack.close()
+    return out
+
+
 def _clip_to_box(o_np, v_np):
     """Entry and exit parameters of each ray with the box [-1, 1]^3 (slab test)."""
     import numpy as np
@@ -531,6 +624,8 @@ def main():
                     help="also time the rows of the paper's Table 3 at 512^2 in fixed-iteration mode")
     ap.add_argument("--fit-full", action="store_true",
                     help="also run the whole 2000-step fit, its quality and a 1080p render of the fitted net")
+    ap.add_argument("--mesh", action="store_true",
+                    help="also time neural normal mapping onto the 512^3 marching-tetrahedra mesh of the (64,1) level")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -572,6 +667,8 @@ def main():
     nesting = run_nesting(args.workload, args.precision) if args.nesting else None
     capacity = run_capacity() if args.capacity else None
     table3 = run_table3([f for f in ("fp32", "bf16") if f in forms] or [args.precision]) if args.table3 else None
+    mesh = [run_mesh(args.workload, f) for f in (("fp32", "bf16") if "fp32" in forms else (args.precision,))] \
+        if args.mesh else None
 
     cpu = None
     errors = {}
@@ -631,6 +728,7 @@ def main():
         "errors_vs_oracle": errors,
         "fit": fit,
         "table3_fixed_iterations": table3,
+        "mesh_normal_mapping": mesh,
         "nesting": nesting,
         "capacity_sequence": capacity,
         "timing": head["timing"],

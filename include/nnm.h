@@ -269,6 +269,62 @@ int fit_set_step(nnm_fit* fit, int64_t step);
 int nnm_sup_abs_diff(const nnm_stack* s, int level_a, int level_b, int64_t n, uint64_t seed, float lo, float hi,
                      float* out_max, void* stream);
 
+/* ------------------------------------------- neural normal mapping on meshes */
+
+/* Neural normal mapping onto arbitrary points, e.g. the vertices of a triangle
+   mesh (Sec. 5: the detailed normals of a finer scene function are assigned to
+   the vertices of a coarser surface, with no parametrisation):
+     x       device [n][3] float32 points; t device [n] or NULL (time 0)
+     normal  device [n][3] float32 out: grad f_level / |grad f_level| (the
+             analytic gradient of Sec. 5.1), 0 where the gradient vanishes.
+   Same kernels and precision as the normal pass of trace_rays.  n = 0 is a
+   no-op.  Errors: NNM_E_INVAL (null, bad level, n < 0 or n > 2^31 - 2^24). */
+int neural_normal_map(const nnm_stack* stack, int level, int64_t n, const float* x, const float* t,
+                      float* normal, void* stream);
+
+/* Largest grid side of nnm_grid_values / nnm_mesh_extract (node, vertex and
+   triangle ids then fit int32). */
+#define NNM_MESH_MAX_RES 512
+
+/* The scene function f_level at the nodes of a res^3 grid over [lo, hi]^3, the
+   input of the coarse-mesh extraction (Fig. 5 extracts its coarse mesh from a
+   (64,1) network):
+     values  device [res^3] float32 out; node (i, j, k) at index
+             (k res + j) res + i (x fastest), at coordinates
+             float(lo + (hi - lo) i / (res - 1)) evaluated in double, likewise
+             for j and k.
+     t       time of every node (4-D levels, moving base); ignored otherwise.
+   Errors: NNM_E_INVAL (null, bad level, res outside [2, NNM_MESH_MAX_RES],
+   lo >= hi, non-finite box or time). */
+int nnm_grid_values(const nnm_stack* stack, int level, int32_t res, float lo, float hi, float t,
+                    float* values, void* stream);
+
+/* The coarse triangle mesh {f < iso} of a grid of values by marching
+   tetrahedra (the paper uses marching cubes and does not fix the variant; the
+   tetrahedral form gives a closed, consistently oriented surface).  The output
+   is deterministic:
+     - a node is inside when value < iso (NaN is outside);
+     - node (i, j, k) owns the edges to node + D for D in the order (1,0,0)
+       (0,1,0) (0,0,1) (1,1,0) (1,0,1) (0,1,1) (1,1,1); an edge whose ends differ
+       holds one vertex at x0 + (iso - v0) / (v1 - v0) (x1 - x0), and vertices
+       are numbered in (node, edge) order;
+     - the cube at node (i, j, k) (all < res - 1) holds six tetrahedra, one per
+       axis order (a, b, c) in lexicographic order with corners 0, e_a,
+       e_a + e_b, (1,1,1), the middle two swapped for odd orders; triangles come
+       in cube order, then tetrahedron order; every triangle is wound
+       counter-clockwise seen from the outside (value >= iso) side.
+     values  device [res^3] float32, the layout of nnm_grid_values
+     verts   device [max_verts][3] float32 out (the first max_verts vertices)
+     tris    device [max_tris][3] int32 out (vertex ids; the first max_tris)
+     counts  device [2] int64 out: total vertices, total triangles (also when
+             they exceed the capacities; call again with larger arrays then)
+   Runs on the current device.  Allocates stream-ordered scratch of about
+   5 res^3 bytes.  Errors: NNM_E_INVAL (null values or counts, res outside
+   [2, NNM_MESH_MAX_RES], lo >= hi, non-finite box or iso, negative capacity, a
+   null array with a positive capacity), NNM_E_NOMEM, NNM_E_DEVICE. */
+int nnm_mesh_extract(const float* values, int32_t res, float lo, float hi, float iso, int64_t max_verts,
+                     int64_t max_tris, float* verts, int32_t* tris, int64_t* counts, void* stream);
+
 /* -------------------------------------------------------------- profiling */
 
 /* A profiler records a HIP event pair around every kernel that trace_rays

@@ -58,7 +58,7 @@ static int dir_index(int dx, int dy, int dz) {
 
 /* Vertex id of the edge between two corners of the cube at (i, j, k); corners
    are given as offsets in {0,1}^3, one componentwise below the other. */
-static int64_t edge_vertex(const int64_t* edge_id, int res, int i, int j, int k, const int u[3], const int w[3]) {
+static int64_t edge_vertex(const int32_t* edge_id, int res, int i, int j, int k, const int u[3], const int w[3]) {
   const int* lower = (u[0] + u[1] + u[2] <= w[0] + w[1] + w[2]) ? u : w;
   const int* upper = lower == u ? w : u;
   const int d = dir_index(upper[0] - lower[0], upper[1] - lower[1], upper[2] - lower[2]);
@@ -68,12 +68,14 @@ static int64_t edge_vertex(const int64_t* edge_id, int res, int i, int j, int k,
 
 /* counts[0] = vertices, counts[1] = triangles (the full totals); the first
    cap_v vertices and cap_t triangles are written when the arrays are given.
-   Returns 0, or -1 on bad arguments / allocation failure. */
+   Returns 0, or -1 on bad arguments, a grid whose 7 res^3 edge ids overflow
+   int32, or allocation failure. */
 int orc_marching_tets(const float* values, int res, double lo, double hi, float iso, double* verts, int32_t* tris,
                       int64_t cap_v, int64_t cap_t, int64_t* counts) {
   if (!values || !counts || res < 2) return -1;
   const int64_t n_nodes = (int64_t)res * res * res;
-  int64_t* edge_id = (int64_t*)malloc((size_t)n_nodes * 7 * sizeof(int64_t));
+  if (n_nodes * 7 > INT32_MAX) return -1; /* vertex ids are int32 */
+  int32_t* edge_id = (int32_t*)malloc((size_t)n_nodes * 7 * sizeof(int32_t));
   if (!edge_id) return -1;
 
   /* vertices, numbered in (node, edge) order */
@@ -95,7 +97,7 @@ int orc_marching_tets(const float* values, int res, double lo, double hi, float 
             const double p1[3] = {coord(lo, hi, res, i1), coord(lo, hi, res, j1), coord(lo, hi, res, k1)};
             for (int c = 0; c < 3; ++c) verts[3 * nv + c] = p0[c] + t * (p1[c] - p0[c]);
           }
-          edge_id[node * 7 + d] = nv++;
+          edge_id[node * 7 + d] = (int32_t)nv++;
         }
       }
 

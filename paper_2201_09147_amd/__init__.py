@@ -8,8 +8,10 @@ streams (default: the current stream).
 
 Entry points (same names as the C ABI in include/nnm.h):
   load_siren_stack, free_siren_stack, trace_rays, analytic_normal,
-  nnm_net_eval, nnm_sup_abs_diff, nnm_validate_stack, nnm_read_net_file, nnm_sync
-plus ``render`` (allocates outputs and calls trace_rays), the fitting entry
+  nnm_net_eval, nnm_sup_abs_diff, neural_normal_map, nnm_grid_values,
+  nnm_mesh_extract, nnm_validate_stack, nnm_read_net_file, nnm_sync
+plus ``render`` (allocates outputs and calls trace_rays), ``extract_mesh`` and
+``mesh_neural_normal_map`` (coarse mesh + fine normals), the fitting entry
 points (``Fit`` over fit_create / fit_step, siren_forward_tangent,
 siren_backward) and ``paper_2201_09147_amd.autograd.SirenFn``.
 """
@@ -35,6 +37,11 @@ from ._binding import (  # noqa: F401
     nnm_net_eval,
     nnm_sup_abs_diff,
     nesting_thresholds,
+    neural_normal_map,
+    nnm_grid_values,
+    nnm_mesh_extract,
+    extract_mesh,
+    mesh_neural_normal_map,
     nnm_validate_stack,
     nnm_level_lipschitz_bound,
     nnm_read_net_file,

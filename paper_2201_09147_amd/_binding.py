@@ -76,6 +76,10 @@ def load_library():
         "analytic_normal": ([P, c_int, c_int64, P, P, P, P, P], c_int),
         "nnm_net_eval": ([P, c_int, c_int64, P, P, P, P, P], c_int),
         "nnm_sup_abs_diff": ([P, c_int, c_int, c_int64, ctypes.c_uint64, ctypes.c_float, ctypes.c_float, P, P], c_int),
+        "neural_normal_map": ([P, c_int, c_int64, P, P, P, P], c_int),
+        "nnm_grid_values": ([P, c_int, c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float, P, P], c_int),
+        "nnm_mesh_extract": ([P, c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float, c_int64, c_int64, P, P, P,
+                              P], c_int),
         "nnm_read_net_file": ([ctypes.c_char_p, P, P, P, P, P], c_int),
         "nnm_free": ([P], None),
         "nnm_param_count": ([c_int32, c_int32, c_int32], c_int64),
@@ -389,6 +393,88 @@ def nesting_thresholds(stack: Stack, n: int = 1 << 24, seed: int = 0, lo: float 
         for i in range(m - 1, 0, -1):
             deltas[i - 1] = deltas[i] + eps[i - 1]
     return deltas, eps
+
+
+def neural_normal_map(stack: Stack, level: int, x, t=None, normal=None, stream=None):
+    """Unit normals of f_level at points x[n, 3] (neural_normal_map); returns the normal tensor."""
+    import torch
+    n = int(x.shape[0])
+    dev = stack.device
+    if normal is None:
+        normal = torch.empty((n, 3), dtype=torch.float32, device=torch.device("cuda", dev))
+    _check(load_library().neural_normal_map(
+        stack.handle, int(level), n, _dev_ptr(x, torch.float32, (n, 3), "x", dev, False),
+        _dev_ptr(t, torch.float32, (n,), "t", dev), _dev_ptr(normal, torch.float32, (n, 3), "normal", dev, False),
+        _stream_ptr(stream, dev)))
+    return normal
+
+
+def nnm_grid_values(stack: Stack, level: int, res: int, lo: float = -1.0, hi: float = 1.0, t: float = 0.0,
+                    values=None, stream=None):
+    """f_level at the res^3 grid nodes (nnm_grid_values); returns values[res, res, res] indexed [k, j, i]."""
+    import torch
+    dev = stack.device
+    if values is None:
+        values = torch.empty((res, res, res), dtype=torch.float32, device=torch.device("cuda", dev))
+    _check(load_library().nnm_grid_values(
+        stack.handle, int(level), int(res), ctypes.c_float(lo), ctypes.c_float(hi), ctypes.c_float(t),
+        _dev_ptr(values, torch.float32, (res, res, res), "values", dev, False), _stream_ptr(stream, dev)))
+    return values
+
+
+def nnm_mesh_extract(values, lo: float = -1.0, hi: float = 1.0, iso: float = 0.0, verts=None, tris=None,
+                     counts=None, stream=None):
+    """Marching tetrahedra into caller-allocated verts[max_v, 3] / tris[max_t, 3] (nnm_mesh_extract).
+
+    Asynchronous; counts (int64 [2], allocated when None) receives the totals,
+    which exceed the capacities when the arrays were too small.  Returns counts."""
+    import torch
+    res = int(values.shape[0])
+    dev = values.device.index if values.device.index is not None else 0
+    if counts is None:
+        counts = torch.empty(2, dtype=torch.int64, device=values.device)
+    max_v = 0 if verts is None else int(verts.shape[0])
+    max_t = 0 if tris is None else int(tris.shape[0])
+    with torch.cuda.device(dev):
+        _check(load_library().nnm_mesh_extract(
+            _dev_ptr(values, torch.float32, (res, res, res), "values", dev, False), res, ctypes.c_float(lo),
+            ctypes.c_float(hi), ctypes.c_float(iso), max_v, max_t,
+            _dev_ptr(verts, torch.float32, (max_v, 3), "verts", dev), _dev_ptr(tris, torch.int32, (max_t, 3), "tris", dev),
+            _dev_ptr(counts, torch.int64, (2,), "counts", dev, False), _stream_ptr(stream, dev)))
+    return counts
+
+
+def extract_mesh(values, lo: float = -1.0, hi: float = 1.0, iso: float = 0.0, capacity=(1 << 20, 1 << 21),
+                 stream=None):
+    """nnm_mesh_extract with allocation: (verts[nv, 3], tris[nt, 3]), calling again with exact
+    capacities when the first guess was too small (one host synchronisation per call)."""
+    import torch
+    dev = values.device
+    max_v, max_t = capacity
+    for _ in range(2):
+        verts = torch.empty((max_v, 3), dtype=torch.float32, device=dev)
+        tris = torch.empty((max_t, 3), dtype=torch.int32, device=dev)
+        counts = nnm_mesh_extract(values, lo, hi, iso, verts, tris, stream=stream)
+        nv, nt = (int(c) for c in counts.cpu())
+        if nv <= max_v and nt <= max_t:
+            return verts[:nv], tris[:nt]
+        max_v, max_t = max(nv, 1), max(nt, 1)
+    raise NnmError(-7, "mesh counts changed between calls")
+
+
+def mesh_neural_normal_map(stack: Stack, coarse_level: int, fine_level: int, res: int, lo: float = -1.0,
+                           hi: float = 1.0, iso: float = 0.0, t: float = 0.0, stream=None):
+    """The triangle-mesh form of neural normal mapping: the coarse mesh of f_coarse by
+    nnm_grid_values + nnm_mesh_extract, with the normals of f_fine at its vertices
+    (neural_normal_map).  Returns (verts, tris, normals)."""
+    values = nnm_grid_values(stack, coarse_level, res, lo, hi, t, stream=stream)
+    verts, tris = extract_mesh(values, lo, hi, iso, stream=stream)
+    tt = None
+    if t != 0.0:
+        import torch
+        tt = torch.full((verts.shape[0],), float(t), dtype=torch.float32, device=verts.device)
+    normals = neural_normal_map(stack, fine_level, verts, tt, stream=stream) if verts.shape[0] else verts.clone()
+    return verts, tris, normals
 
 
 def nnm_sync(stream=None, device: int = 0):

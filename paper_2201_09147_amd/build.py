@@ -18,7 +18,8 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnnm.so")
 
 ARCH = os.environ.get("NNM_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["nnm_api.cpp", "trace_kernels.hip", "trace_ws.hip", "fit_kernels.hip", "nesting_kernels.hip"]
+SOURCES = ["nnm_api.cpp", "trace_kernels.hip", "trace_ws.hip", "fit_kernels.hip", "nesting_kernels.hip",
+           "mesh_kernels.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}"]

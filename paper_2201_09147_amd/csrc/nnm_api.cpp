@@ -699,6 +699,107 @@ int nnm_sup_abs_diff(const nnm_stack* s, int level_a, int level_b, int64_t n, ui
   return rc;
 }
 
+int neural_normal_map(const nnm_stack* s, int level, int64_t n, const float* x, const float* t, float* normal,
+                      void* stream) {
+  g_err.clear();
+  if (!s) return fail(NNM_E_INVAL, "null stack");
+  if (level < 0 || level >= s->m) return fail(NNM_E_INVAL, "level %d of %d", level, s->m);
+  if (n < 0) return fail(NNM_E_INVAL, "n = %lld < 0", (long long)n);
+  if (n > (int64_t)INT_MAX - (1 << 24)) return fail(NNM_E_INVAL, "n = %lld too large", (long long)n);
+  if (n == 0) return NNM_OK;
+  if (!x || !normal) return fail(NNM_E_INVAL, "null points or normals");
+  DeviceGuard guard(s->device);
+  if (!guard.ok) return fail(NNM_E_DEVICE, "hipSetDevice(%d) failed", s->device);
+  const auto& lv = s->levels[level];
+  NormalArgs a{};
+  a.L = lv.dev;
+  a.B = s->base;
+  a.t = t;
+  a.normal = normal;
+  a.n = (int)n;
+  a.x = x;
+  hipError_t e;
+  if (lv.dev.ws_ah && s->use_ws) {
+    const long long want = (n + kWsPointsPerBlock - 1) / kWsPointsPerBlock;
+    const int grid = (int)std::max(1LL, std::min(want, (long long)lv.ws_resident[1]));
+    e = launch_normal_ws(s->precision, a, grid, (hipStream_t)stream);
+  } else {
+    const long long want = (n + 31) / 32;
+    const int grid = (int)std::max(1LL, std::min(want, (long long)lv.resident[1]));
+    e = launch_normal(lv.width, s->precision, a, grid, (hipStream_t)stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "normal mapping");
+  return NNM_OK;
+}
+
+int nnm_grid_values(const nnm_stack* s, int level, int32_t res, float lo, float hi, float t, float* values,
+                    void* stream) {
+  g_err.clear();
+  if (!s || !values) return fail(NNM_E_INVAL, "null stack or output");
+  if (level < 0 || level >= s->m) return fail(NNM_E_INVAL, "level %d of %d", level, s->m);
+  if (res < 2 || res > NNM_MESH_MAX_RES) return fail(NNM_E_INVAL, "res = %d outside [2, %d]", res, NNM_MESH_MAX_RES);
+  if (!(lo < hi) || !std::isfinite(lo) || !std::isfinite(hi)) return fail(NNM_E_INVAL, "box [%g, %g]", lo, hi);
+  if (!std::isfinite(t)) return fail(NNM_E_INVAL, "time %g", t);
+  DeviceGuard guard(s->device);
+  if (!guard.ok) return fail(NNM_E_DEVICE, "hipSetDevice(%d) failed", s->device);
+  const auto& lv = s->levels[level];
+  GridArgs a{};
+  a.L = lv.dev;
+  a.B = s->base;
+  a.res = res;
+  a.n = res * res * res;
+  a.lo = lo;
+  a.hi = hi;
+  a.t = t;
+  a.values = values;
+  const hipError_t e = launch_grid_values(lv.width, s->precision, a, s->device, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "grid values");
+  return NNM_OK;
+}
+
+int nnm_mesh_extract(const float* values, int32_t res, float lo, float hi, float iso, int64_t max_verts,
+                     int64_t max_tris, float* verts, int32_t* tris, int64_t* counts, void* stream) {
+  g_err.clear();
+  if (!values || !counts) return fail(NNM_E_INVAL, "null values or counts");
+  if (res < 2 || res > NNM_MESH_MAX_RES) return fail(NNM_E_INVAL, "res = %d outside [2, %d]", res, NNM_MESH_MAX_RES);
+  if (!(lo < hi) || !std::isfinite(lo) || !std::isfinite(hi)) return fail(NNM_E_INVAL, "box [%g, %g]", lo, hi);
+  if (!std::isfinite(iso)) return fail(NNM_E_INVAL, "iso %g", iso);
+  if (max_verts < 0 || max_tris < 0) return fail(NNM_E_INVAL, "negative capacity");
+  if ((max_verts > 0 && !verts) || (max_tris > 0 && !tris)) return fail(NNM_E_INVAL, "null output array");
+  hipStream_t st = (hipStream_t)stream;
+  MeshArgs a{};
+  a.values = values;
+  a.res = res;
+  a.n_nodes = res * res * res;
+  a.n_blocks = mesh_blocks(res);
+  a.n_groups = (a.n_blocks + 1023) / 1024;
+  a.lo = lo;
+  a.hi = hi;
+  a.iso = iso;
+  a.verts = verts;
+  a.tris = tris;
+  a.max_v = max_verts;
+  a.max_t = max_tris;
+  a.counts = (long long*)counts;
+  const size_t off_bt = align256((size_t)a.n_blocks * 4), off_gv = off_bt + align256((size_t)a.n_blocks * 4),
+               off_gt = off_gv + align256((size_t)a.n_groups * 4), off_vo = off_gt + align256((size_t)a.n_groups * 4),
+               off_fl = off_vo + align256((size_t)a.n_nodes * 4), total = off_fl + align256((size_t)a.n_nodes);
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, total, st);
+  if (e != hipSuccess) return fail(NNM_E_NOMEM, "hipMallocAsync(%zu): %s", total, hipGetErrorString(e));
+  char* wb = (char*)ws;
+  a.bsum_v = (int*)wb;
+  a.bsum_t = (int*)(wb + off_bt);
+  a.gsum_v = (int*)(wb + off_gv);
+  a.gsum_t = (int*)(wb + off_gt);
+  a.vert_off = (int*)(wb + off_vo);
+  a.mask = (uint8_t*)(wb + off_fl);
+  int rc = NNM_OK;
+  if ((e = launch_marching_tets(a, st)) != hipSuccess) rc = hip_fail(e, "marching tetrahedra");
+  if ((e = hipFreeAsync(ws, st)) != hipSuccess && rc == NNM_OK) rc = hip_fail(e, "hipFreeAsync");
+  return rc;
+}
+
 int nnm_profiler_create(nnm_profiler** out) {
   if (!out) return fail(NNM_E_INVAL, "null output handle");
   *out = new nnm_profiler();

@@ -51,6 +51,39 @@ struct NormalArgs {
   const int* queue;
   const int* count;
   int n;
+  const float* x;  // non-null: points mode, the point of entry i is x[3 i] (o, v, depth unused)
+};
+
+// Scene-function values at the nodes of a res^3 grid over [lo, hi]^3 (node
+// (i, j, k) at index (k res + j) res + i, coordinate lo + (hi - lo) i / (res - 1)).
+struct GridArgs {
+  DevLevel L;
+  DevBase B;
+  int res;
+  int n;  // res^3
+  float lo, hi;
+  float t;  // time of every node (4-D nets, moving base)
+  float* values;
+};
+
+// Marching tetrahedra over a grid of values (count, block-sum scan, vertices, triangles).
+struct MeshArgs {
+  const float* values;
+  int res;
+  int n_nodes;
+  int n_blocks;       // extraction workgroups (mesh_blocks(res))
+  float lo, hi, iso;
+  int* bsum_v;        // [n_blocks] vertices per block, then their exclusive prefix
+  int* bsum_t;        // [n_blocks] triangles per block, then their exclusive prefix
+  int* gsum_v;        // [n_groups] prefix of vertices per group of 1024 blocks
+  int* gsum_t;        // [n_groups] the same for triangles
+  int n_groups;       // ceil(n_blocks / 1024), at most 1024
+  int* vert_off;      // [n_nodes] id of the first vertex on the node's edges (surface nodes only)
+  uint8_t* mask;      // [n_nodes] inside bits of the node's 8 cube corners (outside corners copy corner 0)
+  float* verts;       // [max_v][3]
+  int* tris;          // [max_t][3]
+  long long max_v, max_t;
+  long long* counts;  // [2] total vertices, total triangles
 };
 
 // Value and gradient at arbitrary points.
@@ -143,6 +176,10 @@ hipError_t launch_points(int width, int prec, const PointsArgs& a, int grid, hip
 hipError_t launch_trace_ws(int prec, const TraceLevelArgs& a, int grid, hipStream_t s);
 hipError_t launch_normal_ws(int prec, const NormalArgs& a, int grid, hipStream_t s);
 int ws_resident_blocks(int prec, int kind, int device);  // kind: 0 trace, 1 normal
+hipError_t launch_grid_values(int width, int prec, const GridArgs& a, int device, hipStream_t s);
+constexpr int kMeshThreads = 256;  // threads of an extraction workgroup
+int mesh_blocks(int res);          // workgroups of the flat extraction passes for a grid side
+hipError_t launch_marching_tets(const MeshArgs& a, hipStream_t s);
 // Workgroups of each kernel kind that fit on the whole device at once.
 int resident_blocks(int width, int prec, int kind, int device);  // kind: 0 trace, 1 normal, 2 points
 

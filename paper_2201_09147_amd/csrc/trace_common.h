@@ -23,4 +23,22 @@ __device__ inline void center_at(const DevBase& B, float t, float& cx, float& cy
   }
 }
 
+// Instantiates CALL(H, P) for every built (width, precision) pair.
+#define NNM_DISPATCH(WIDTH, PREC, CALL)                                   \
+  switch ((WIDTH) * 4 + (PREC)) {                                         \
+    case 32 * 4 + PREC_FP32: { CALL(32, PREC_FP32); } break;              \
+    case 32 * 4 + PREC_BF16: { CALL(32, PREC_BF16); } break;              \
+    case 32 * 4 + PREC_FP16: { CALL(32, PREC_FP16); } break;              \
+    case 64 * 4 + PREC_FP32: { CALL(64, PREC_FP32); } break;              \
+    case 64 * 4 + PREC_BF16: { CALL(64, PREC_BF16); } break;              \
+    case 64 * 4 + PREC_FP16: { CALL(64, PREC_FP16); } break;              \
+    case 128 * 4 + PREC_FP32: { CALL(128, PREC_FP32); } break;            \
+    case 128 * 4 + PREC_BF16: { CALL(128, PREC_BF16); } break;            \
+    case 128 * 4 + PREC_FP16: { CALL(128, PREC_FP16); } break;            \
+    case 256 * 4 + PREC_FP32: { CALL(256, PREC_FP32); } break;            \
+    case 256 * 4 + PREC_BF16: { CALL(256, PREC_BF16); } break;            \
+    case 256 * 4 + PREC_FP16: { CALL(256, PREC_FP16); } break;            \
+    default: return hipErrorInvalidValue;                                 \
+  }
+
 }  // namespace nnm

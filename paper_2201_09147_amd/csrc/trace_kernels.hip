@@ -198,7 +198,8 @@ __global__ void __launch_bounds__(kBlockThreads) k_trace_level(TraceLevelArgs A)
   }
 }
 
-// Forward + three tangent columns at the hit points; unit grad f as the normal.
+// Forward + three tangent columns at the hit points (or at given points); unit
+// grad f as the normal.
 template <int H, int P>
 __global__ void __launch_bounds__(kBlockThreads) k_normal(NormalArgs A) {
   __shared__ NetSmem<H> sm;
@@ -217,10 +218,16 @@ __global__ void __launch_bounds__(kBlockThreads) k_normal(NormalArgs A) {
     const int ray = (slot < n_in) ? (A.queue ? A.queue[slot] : slot) : -1;
     float x = 0.f, y = 0.f, z = 0.f, tt = 0.f;
     if (ray >= 0) {
-      const float tau = A.depth[ray];
-      x = fmaf(tau, A.v[3 * ray + 0], A.o[3 * ray + 0]);
-      y = fmaf(tau, A.v[3 * ray + 1], A.o[3 * ray + 1]);
-      z = fmaf(tau, A.v[3 * ray + 2], A.o[3 * ray + 2]);
+      if (A.x) {
+        x = A.x[3 * ray + 0];
+        y = A.x[3 * ray + 1];
+        z = A.x[3 * ray + 2];
+      } else {
+        const float tau = A.depth[ray];
+        x = fmaf(tau, A.v[3 * ray + 0], A.o[3 * ray + 0]);
+        y = fmaf(tau, A.v[3 * ray + 1], A.o[3 * ray + 1]);
+        z = fmaf(tau, A.v[3 * ray + 2], A.o[3 * ray + 2]);
+      }
       tt = A.t ? A.t[ray] : 0.f;
     }
     float cx, cy;
@@ -313,23 +320,6 @@ hipError_t launch_zero_ints(int* p, int count, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_ints, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
   return hipGetLastError();
 }
-
-#define NNM_DISPATCH(WIDTH, PREC, CALL)                                   \
-  switch ((WIDTH) * 4 + (PREC)) {                                         \
-    case 32 * 4 + PREC_FP32: { CALL(32, PREC_FP32); } break;              \
-    case 32 * 4 + PREC_BF16: { CALL(32, PREC_BF16); } break;              \
-    case 32 * 4 + PREC_FP16: { CALL(32, PREC_FP16); } break;              \
-    case 64 * 4 + PREC_FP32: { CALL(64, PREC_FP32); } break;              \
-    case 64 * 4 + PREC_BF16: { CALL(64, PREC_BF16); } break;              \
-    case 64 * 4 + PREC_FP16: { CALL(64, PREC_FP16); } break;              \
-    case 128 * 4 + PREC_FP32: { CALL(128, PREC_FP32); } break;            \
-    case 128 * 4 + PREC_BF16: { CALL(128, PREC_BF16); } break;            \
-    case 128 * 4 + PREC_FP16: { CALL(128, PREC_FP16); } break;            \
-    case 256 * 4 + PREC_FP32: { CALL(256, PREC_FP32); } break;            \
-    case 256 * 4 + PREC_BF16: { CALL(256, PREC_BF16); } break;            \
-    case 256 * 4 + PREC_FP16: { CALL(256, PREC_FP16); } break;            \
-    default: return hipErrorInvalidValue;                                 \
-  }
 
 hipError_t launch_trace_level(int width, int prec, const TraceLevelArgs& a, int grid, hipStream_t s) {
 #define CALL(H, P) hipLaunchKernelGGL((k_trace_level<H, P>), dim3(grid), dim3(kBlockThreads), 0, s, a)

@@ -668,13 +668,21 @@ struct NormalCtl {
   }
   __device__ inline void fetch_data(const NormalArgs& A) {
     if (p_ray >= 0) {
-      p_ox = A.o[3 * p_ray + 0];
-      p_oy = A.o[3 * p_ray + 1];
-      p_oz = A.o[3 * p_ray + 2];
-      p_vx = A.v[3 * p_ray + 0];
-      p_vy = A.v[3 * p_ray + 1];
-      p_vz = A.v[3 * p_ray + 2];
-      p_tau = A.depth[p_ray];
+      if (A.x) {
+        // points mode: tau = 0 and v = 0 make the end point x itself
+        p_ox = A.x[3 * p_ray + 0];
+        p_oy = A.x[3 * p_ray + 1];
+        p_oz = A.x[3 * p_ray + 2];
+        p_vx = p_vy = p_vz = p_tau = 0.f;
+      } else {
+        p_ox = A.o[3 * p_ray + 0];
+        p_oy = A.o[3 * p_ray + 1];
+        p_oz = A.o[3 * p_ray + 2];
+        p_vx = A.v[3 * p_ray + 0];
+        p_vy = A.v[3 * p_ray + 1];
+        p_vz = A.v[3 * p_ray + 2];
+        p_tau = A.depth[p_ray];
+      }
       p_t = A.t ? A.t[p_ray] : 0.f;
     }
   }

@@ -126,3 +126,24 @@ def test_product_path_does_not_reference_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower(), f
+
+
+def test_mesh_entry_points_reject_bad_arguments_before_device_use(lib):
+    """nnm_mesh_extract / nnm_grid_values / neural_normal_map validate on the host."""
+    import ctypes
+    fake = ctypes.c_void_p(256)  # never dereferenced: every call below fails validation first
+    f = ctypes.c_float
+    ext = lib.nnm_mesh_extract
+    assert ext(None, 8, f(-1), f(1), f(0), 0, 0, None, None, fake, None) == -1
+    assert ext(fake, 8, f(-1), f(1), f(0), 0, 0, None, None, None, None) == -1
+    assert ext(fake, 1, f(-1), f(1), f(0), 0, 0, None, None, fake, None) == -1
+    assert ext(fake, 513, f(-1), f(1), f(0), 0, 0, None, None, fake, None) == -1
+    assert "res = 513" in lib.nnm_last_error().decode()
+    assert ext(fake, 8, f(1), f(-1), f(0), 0, 0, None, None, fake, None) == -1
+    assert ext(fake, 8, f(-1), f(float("inf")), f(0), 0, 0, None, None, fake, None) == -1
+    assert ext(fake, 8, f(-1), f(1), f(float("nan")), 0, 0, None, None, fake, None) == -1
+    assert ext(fake, 8, f(-1), f(1), f(0), -1, 0, None, None, fake, None) == -1
+    assert ext(fake, 8, f(-1), f(1), f(0), 4, 0, None, None, fake, None) == -1
+    assert ext(fake, 8, f(-1), f(1), f(0), 0, 4, fake, None, fake, None) == -1
+    assert lib.nnm_grid_values(None, 0, 8, f(-1), f(1), f(0), fake, None) == -1
+    assert lib.neural_normal_map(None, 0, 4, fake, None, fake, None) == -1
