@@ -42,7 +42,7 @@ def normal_hidden_flops(net) -> int:
     return 4 * hidden_flops(net)
 
 
-def run_form(scene, precision, o, v, t, steps, warmup):
+def run_form(scene, precision, o, v, t, steps, warmup, final_level=-1, normal_level=-1):
     import torch
     import paper_2201_09147_amd as nnm
     dev = torch.device("cuda", 0)
@@ -60,7 +60,7 @@ def run_form(scene, precision, o, v, t, steps, warmup):
         "status": torch.empty(n, dtype=torch.uint8, device=dev),
     }
     prof = nnm.Profiler()
-    params = nnm.TraceParams(scene.step_scale, scene.eps, scene.far, scene.max_steps)
+    params = nnm.TraceParams(scene.step_scale, scene.eps, scene.far, scene.max_steps, final_level, normal_level)
 
     def call(p):
         nnm.trace_rays(stack, p, o, v, t, out["depth"], out["hit"], out["normal"], out["steps"],
@@ -69,8 +69,9 @@ def run_form(scene, precision, o, v, t, steps, warmup):
     for _ in range(warmup):
         call(params)
     torch.cuda.synchronize()
-    log(f"[{precision}] warmup done ({warmup} steps)")
-    timed = nnm.TraceParams(scene.step_scale, scene.eps, scene.far, scene.max_steps, profiler=prof)
+    log(f"[{precision}] warmup done ({warmup} steps, final level {final_level}, normal level {normal_level})")
+    timed = nnm.TraceParams(scene.step_scale, scene.eps, scene.far, scene.max_steps, final_level, normal_level,
+                            profiler=prof)
     # per-call HIP events on the calls' (current) stream, plus the wall clock around all K calls
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
@@ -86,7 +87,8 @@ def run_form(scene, precision, o, v, t, steps, warmup):
               "p90_ms": round(per_call[min(len(per_call) - 1, int(0.9 * len(per_call)))], 4),
               "load_ms": round(load_ms, 3)}
     report = prof.report()
-    log(f"[{precision}] {steps} steps: {ms:.3f} ms/step, {n / ms * 1e3 / 1e9:.3f} Grays/s; per call median "
+    tag = precision if final_level < 0 else f"{precision} NNM {final_level}->{normal_level}"
+    log(f"[{tag}] {steps} steps: {ms:.3f} ms/step, {n / ms * 1e3 / 1e9:.3f} Grays/s; per call median "
         f"{timing['median_ms']:.3f} min {timing['min_ms']:.3f} p90 {timing['p90_ms']:.3f} ms; "
         f"stack load {load_ms:.1f} ms")
     evals = out["steps"].to(torch.int64).sum(dim=0).cpu().tolist()
@@ -615,6 +617,8 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16,fp16")
     ap.add_argument("--cpu-rows-every", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-nnm-variant", action="store_true",
+                    help="skip the neural-normal-mapping variant (trace to level m-2, normals of level m-1)")
     ap.add_argument("--fit-steps", type=int, default=10, help="fitting steps to time (0: skip)")
     ap.add_argument("--capacity", action="store_true",
                     help="also fit (32,1), (64,1), (256,2) to the torus, nest them by Prop. 1 and render at 1080p")
@@ -660,6 +664,13 @@ def main():
     if args.precision not in forms:
         forms.append(args.precision)
     results = {f: run_form(scene, f, o, v, t, args.steps, args.warmup) for f in forms}
+    # neural normal mapping variant (Sec. 5): trace to the second-finest level's
+    # surface, normals of the finest level there
+    m = len(scene.levels)
+    nnm_res = {}
+    if m >= 2 and not args.no_nnm_variant:
+        nnm_res = {f: run_form(scene, f, o, v, t, args.steps, args.warmup, final_level=m - 2, normal_level=m - 1)
+                   for f in forms}
 
     fit = run_fit(args.fit_steps, 2) if args.fit_steps > 0 else None
     if fit is not None and args.fit_full:
@@ -705,6 +716,45 @@ def main():
                          "common_hits": int(both.sum())}
             log(f"[{f}] vs oracle: {errors[f]}")
 
+    nnm_block = None
+    if nnm_res:
+        nnm_block = {"final_level": m - 2, "normal_level": m - 1, "forms": {}}
+        if cpu is not None:
+            # oracle of the variant on every 8th row of the frame
+            rows8 = np.arange(0, scene.height, 8)
+            idx8 = (rows8[:, None] * scene.width + np.arange(scene.width)[None, :]).reshape(-1)
+            c0 = time.perf_counter()
+            ref8 = orc.trace(scene, o_np[idx8], v_np[idx8], None if t_np is None else t_np[idx8],
+                             final_level=m - 2, normal_level=m - 1)
+            log(f"oracle of the NNM variant on {idx8.size} rays: {time.perf_counter() - c0:.1f} s")
+        for f, r in nnm_res.items():
+            full = results[f]["outputs"]
+            g = r["outputs"]
+            both = (g["hit"] == 1) & (full["hit"] == 1)
+            a64, b64 = g["normal"][both].astype(np.float64), full["normal"][both].astype(np.float64)
+            ang = np.degrees(np.arctan2(np.linalg.norm(np.cross(a64, b64), axis=1), np.sum(a64 * b64, axis=1)))
+            entry = {"rays_per_s": round(r["rays_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                     "timing": r["timing"], "hits": r["hits"], "evals_per_level": r["evals_per_level"],
+                     "kernels": r["kernels"],
+                     "speedup_vs_full": round(results[f]["ms_per_step"] / r["ms_per_step"], 3),
+                     "vs_full_trace": {"mask_agreement": round(float(np.mean(g["hit"] == full["hit"])), 6),
+                                       "depth_max_abs_diff": float(np.abs(g["depth"][both] - full["depth"][both]).max()),
+                                       "normal_angle_mean_deg": float(ang.mean()),
+                                       "normal_angle_p99_deg": float(np.quantile(ang, 0.99))}}
+            if cpu is not None:
+                gg = {k: val[idx8] for k, val in g.items()}
+                hit, rhit = gg["hit"] == 1, ref8["hit"] == 1
+                bb = hit & rhit
+                a64, b64 = gg["normal"][bb].astype(np.float64), ref8["normal"][bb]
+                ang = np.degrees(np.arctan2(np.linalg.norm(np.cross(a64, b64), axis=1), np.sum(a64 * b64, axis=1)))
+                entry["errors_vs_oracle"] = {"rays": int(idx8.size), "mask_agreement": round(float(np.mean(hit == rhit)), 6),
+                                             "depth_max_abs_err": float(np.abs(gg["depth"][bb] - ref8["depth"][bb]).max()),
+                                             "normal_angle_mean_deg": float(ang.mean()),
+                                             "normal_angle_max_deg": float(ang.max())}
+            nnm_block["forms"][f] = entry
+            log(f"[{f} NNM] {entry['rays_per_s'] / 1e6:.1f} Mrays/s, {entry['speedup_vs_full']}x the full trace; "
+                f"vs full: {entry['vs_full_trace']}")
+
     head = results[args.precision]
     line = {
         "metric": METRIC,
@@ -727,6 +777,7 @@ def main():
         "cpu_baseline": cpu,
         "errors_vs_oracle": errors,
         "fit": fit,
+        "nnm_variant": nnm_block,
         "table3_fixed_iterations": table3,
         "mesh_normal_mapping": mesh,
         "nesting": nesting,
