@@ -44,6 +44,11 @@ constexpr float kTwoPi = 6.28318530717958647692f;
 #ifndef NNM_RING_LOWP
 #define NNM_RING_LOWP 4
 #endif
+// Ring depth for H = 64 (its four k-steps fit a depth-4 ring; a shallower ring
+// frees registers for occupancy).
+#ifndef NNM_RING_LOWP_64
+#define NNM_RING_LOWP_64 4
+#endif
 
 // Compiler barrier: memory operations are not moved across it, which keeps
 // loop-invariant table reads from being hoisted into long-lived registers.
@@ -232,8 +237,10 @@ struct SirenTile {
     } else {
       typedef HiddenOps<P> Ops;
       typedef typename Ops::frag_t frag_t;
-      constexpr int kRing = NNM_RING_LOWP;
       constexpr int KS = 2 * MB;
+      // never deeper than the layer's k-steps (no fragment past the layer is read)
+      constexpr int kRingWant = H == 64 ? NNM_RING_LOWP_64 : NNM_RING_LOWP;
+      constexpr int kRing = kRingWant < KS ? kRingWant : KS;
       frag_t bfr[KS];
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {

@@ -23,6 +23,16 @@ __device__ inline void center_at(const DevBase& B, float t, float& cx, float& cy
   }
 }
 
+// Position of the idx-th popped entry of a level's input queue of n entries.
+// The previous level appends rays in the order they finish, so the slowest
+// rays of that level (grazing ones, which are also slow at this level) sit at
+// the end; reading the queue backwards admits them first and shortens the
+// drain tail.  Results do not depend on the order.
+#ifndef NNM_QUEUE_LIFO
+#define NNM_QUEUE_LIFO 1
+#endif
+__device__ inline int queue_slot(int idx, int n) { return NNM_QUEUE_LIFO ? n - 1 - idx : idx; }
+
 // Instantiates CALL(H, P) for every built (width, precision) pair.
 #define NNM_DISPATCH(WIDTH, PREC, CALL)                                   \
   switch ((WIDTH) * 4 + (PREC)) {                                         \

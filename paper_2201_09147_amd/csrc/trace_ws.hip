@@ -382,7 +382,7 @@ struct TraceCtl {
       const int q = ((lane - s_head) & 63) - s_count;
       if (q >= 0 && q < add) {
         const int idx = cur + q;
-        s_ray = A.in_queue ? A.in_queue[idx] : idx;
+        s_ray = A.in_queue ? A.in_queue[queue_slot(idx, n_in)] : idx;
         s_ox = A.o[3 * s_ray + 0];
         s_oy = A.o[3 * s_ray + 1];
         s_oz = A.o[3 * s_ray + 2];
