@@ -110,15 +110,15 @@ __device__ inline float pipe_act(float v, const PipeLane& pl) {
 template <int P>
 struct PipeWeights {
   typedef typename HiddenOps<P>::frag_t frag_t;
-  float w0[2][3];  // layer-0 row blocks: its own, and (role 1 when role 0 hands it over) block 0
+  float w0[2][3];  // the operands of the (up to two) first-layer row blocks this wave computes
   frag_t w[2][16];
 
-  __device__ inline void load(const DevLevel& L, int wave, int lane) {
+  __device__ inline void load(const DevLevel& L, int wave, int lane, int blk0, int blk1) {
     const int team = wave >> 2, tw = wave & 3;
 #pragma unroll
     for (int ks = 0; ks < 3; ++ks) {
-      w0[0][ks] = L.ws_a0[(wave * 3 + ks) * 64 + lane];
-      w0[1][ks] = wave == 1 ? L.ws_a0[ks * 64 + lane] : 0.f;
+      w0[0][ks] = blk0 >= 0 ? L.ws_a0[(blk0 * 3 + ks) * 64 + lane] : 0.f;
+      w0[1][ks] = blk1 >= 0 ? L.ws_a0[(blk1 * 3 + ks) * 64 + lane] : 0.f;
     }
     const frag_t* WA = (const frag_t*)L.ws_ah;
 #pragma unroll
@@ -290,6 +290,33 @@ __device__ inline void pipe_team1_layer0(PipeSmem<C>& sm, const PipeWeights<P>& 
   if (OFF0 && wave == 1) pipe_layer0<C, P, TAN>(W, 1, sm.xin[s & 1], sm.act0[s & 1], L.d_in, 0, pl);
 }
 
+#ifndef NNM_NORMAL_L0_MODE
+#define NNM_NORMAL_L0_MODE 1
+#endif
+// First-layer row blocks (0..7, 32 rows each) of the normal kernel per role,
+// -1 for none.  Its team-2 waves carry the sines and output dot products of
+// four columns per point and set the stage time, so roles 5-7 compute no
+// first-layer block; roles 1-3 compute blocks w and w + 4.  Mode 0 is the
+// tracing kernel's assignment (one block per wave, role 1 taking the control
+// wave's); modes 2 and 3 move block 4 to role 0 or block 0 to role 4.
+__device__ inline int normal_blk(int wave, int slot) {
+  constexpr int mode = NNM_NORMAL_L0_MODE;
+  if (mode == 0) return slot == 0 ? (wave == 0 ? -1 : wave) : (wave == 1 ? 0 : -1);
+  if (wave >= 1 && wave <= 3) return slot == 0 ? wave : wave + 4;
+  if (wave == 0) return slot == 0 ? (mode == 3 ? -1 : 0) : (mode == 2 ? 4 : -1);
+  if (wave == 4) return slot == 0 ? (mode == 2 ? -1 : 4) : (mode == 3 ? 0 : -1);
+  return -1;
+}
+
+template <int C, int P>
+__device__ inline void pipe_normal_layer0(PipeSmem<C>& sm, const PipeWeights<P>& W, const DevLevel& L, int s, int wave,
+                                          const PipeLane& pl) {
+  if (!sm.tlive[s & 7]) return;
+  const int b0 = normal_blk(wave, 0), b1 = normal_blk(wave, 1);
+  if (b0 >= 0) pipe_layer0<C, P, true>(W, 0, sm.xin[s & 1], sm.act0[s & 1], L.d_in, b0, pl);
+  if (b1 >= 0) pipe_layer0<C, P, true>(W, 1, sm.xin[s & 1], sm.act0[s & 1], L.d_in, b1, pl);
+}
+
 template <int C, bool TAN, bool RED>
 __device__ inline void pipe_team2_out(PipeSmem<C>& sm, const f32x16_t (&acc)[(C / 32)][2], int s, int wave,
                                       const PipeLane& pl) {
@@ -303,11 +330,13 @@ __device__ inline void pipe_team2_out(PipeSmem<C>& sm, const f32x16_t (&acc)[(C 
   }
 }
 
-template <int C, int P, bool TAN>
+// L0: this call computes the wave's first-layer block (the normal kernel does
+// its first layer in pipe_normal_layer0 instead).
+template <int C, int P, bool TAN, bool L0 = true>
 __device__ inline void pipe_team2_in(PipeSmem<C>& sm, const PipeWeights<P>& W, const DevLevel& L,
                                      f32x16_t (&acc)[(C / 32)][2], int s, int wave, const PipeLane& pl) {
   const int tw = wave & 3;
-  if (sm.tlive[s & 7]) pipe_layer0<C, P, TAN>(W, 0, sm.xin[s & 1], sm.act0[s & 1], L.d_in, wave, pl);
+  if (L0 && sm.tlive[s & 7]) pipe_layer0<C, P, TAN>(W, 0, sm.xin[s & 1], sm.act0[s & 1], L.d_in, wave, pl);
   if (sm.tlive[(s + 6) & 7]) {
     pipe_hidden<C, P>(W, sm.act1[s & 1], (TAN && pl.c) ? sm.zeros : sm.bias[1], acc, tw, pl);
   } else {
@@ -610,7 +639,7 @@ struct TraceCtl {
 template <int P, bool RED, bool TEAM2>
 __device__ inline void trace_body(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int wave, int lane) {
   PipeWeights<P> W;
-  W.load(A.L, wave, lane);
+  W.load(A.L, wave, lane, wave, wave == 1 ? 0 : -1);  // role 1 also computes the control wave's block
   const PipeLane pl = pipe_lane<false>(lane);
   const bool ctl_wave = !TEAM2 && wave == 0;
   TraceCtl ctl;
@@ -761,7 +790,7 @@ struct NormalCtl {
 template <int P, bool RED, bool TEAM2>
 __device__ inline void normal_body(PipeSmem<kNormalCols>& sm, const NormalArgs& A, int wave, int lane) {
   PipeWeights<P> W;
-  W.load(A.L, wave, lane);
+  W.load(A.L, wave, lane, normal_blk(wave, 0), normal_blk(wave, 1));
   const PipeLane pl = pipe_lane<true>(lane);
   const bool ctl_wave = !TEAM2 && wave == 0;
   NormalCtl ctl;
@@ -775,10 +804,11 @@ __device__ inline void normal_body(PipeSmem<kNormalCols>& sm, const NormalArgs& 
     if (!TEAM2) {
       pipe_team1_hidden<kNormalCols, P, true, RED>(sm, W, acc, s, wave, pl);
       if (ctl_wave) ctl.step(sm, A, s, lane);
-      pipe_team1_layer0<kNormalCols, P, true, true>(sm, W, A.L, s, wave, pl);
+      pipe_normal_layer0<kNormalCols, P>(sm, W, A.L, s, wave, pl);
     } else {
       pipe_team2_out<kNormalCols, true, RED>(sm, acc, s, wave, pl);
-      pipe_team2_in<kNormalCols, P, true>(sm, W, A.L, acc, s, wave, pl);
+      pipe_normal_layer0<kNormalCols, P>(sm, W, A.L, s, wave, pl);
+      pipe_team2_in<kNormalCols, P, true, false>(sm, W, A.L, acc, s, wave, pl);
     }
     __syncthreads();
   }
