@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kBlockThreads) k_fit_fb(FitArgs A) {
     // ---- forward: store pre-activations (revolutions) and layer inputs
     f32x16_t acc[MB];
     NNM_MEM_FENCE();
-    tile.layer0_acc(A.L, in, c, acc);
+    tile.layer0_acc(&sm, A.L, in, c, acc);
     for (int layer = 0; layer < K; ++layer) {
       if (layer > 0) tile.hidden_acc(&sm, A.L, layer, c, acc);
       // [column][neuron] slabs: rows 32 mb + 8 b + 4 g .. +3 are 16 contiguous bytes

@@ -54,11 +54,22 @@ constexpr float kTwoPi = 6.28318530717958647692f;
 // loop-invariant table reads from being hoisted into long-lived registers.
 #define NNM_MEM_FENCE() __asm__ volatile("" ::: "memory")
 
-// Per-workgroup copy of the small per-network tables (read with broadcast).
+// Widths whose first-layer operand and first hidden layer are held in LDS
+// (then the tile's only global loads are its rays': a prefetch of ray data is
+// not caught by waits on weight loads, and the weights come at LDS latency).
+#ifndef NNM_LDS_WEIGHTS_MAX_H
+#define NNM_LDS_WEIGHTS_MAX_H 64
+#endif
+
+// Per-workgroup copy of the per-network tables (read with broadcast) and, for
+// narrow networks, of the first two layers' MFMA operands.
 template <int H>
 struct NetSmem {
+  static constexpr bool kCache = H <= NNM_LDS_WEIGHTS_MAX_H;
   float wk[H];                   // output weights, accumulator layout
   float bh[(kMaxSine - 1) * H];  // hidden biases / 2 pi, accumulator layout
+  float a0[kCache ? 3 * (H / 32) * 64 : 1];  // layer-0 A operand (copy of DevLevel::a0)
+  uint4 ah1[kCache ? H * H / 4 : 1];         // hidden layer 1 A fragments (H * H * 4 bytes: the fp32 size)
 };
 
 template <int H>
@@ -66,6 +77,15 @@ __device__ inline void stage_net(NetSmem<H>* sm, const DevLevel& L) {
   for (int i = threadIdx.x; i < H; i += blockDim.x) sm->wk[i] = L.wk[i];
   const int nb = (L.n_sine - 1) * H;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) sm->bh[i] = L.bh[i];
+  if constexpr (NetSmem<H>::kCache) {
+    for (int i = threadIdx.x; i < 3 * (H / 32) * 64; i += blockDim.x) sm->a0[i] = L.a0[i];
+    if (L.n_sine >= 2) {
+      // one hidden layer: ah_stride bytes (H * H * element size, at most the array)
+      const int n16 = (int)min((long long)(H * H / 4), L.ah_stride / 16);
+      const uint4* src = (const uint4*)L.ah;
+      for (int i = threadIdx.x; i < n16; i += blockDim.x) sm->ah1[i] = src[i];
+    }
+  }
   __syncthreads();
 }
 
@@ -193,7 +213,7 @@ struct SirenTile {
   }
 
   // Layer-0 accumulators: W_0 [in | 1] / 2 pi (tangent columns: W_0[:, c-1] / 2 pi).
-  __device__ inline void layer0_acc(const DevLevel& L, float4 in, int c, f32x16_t* acc) {
+  __device__ inline void layer0_acc(const NetSmem<H>* sm, const DevLevel& L, float4 in, int c, f32x16_t* acc) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 5;
     const int ks0 = L.d_in == 4 ? 3 : 2;
@@ -201,7 +221,7 @@ struct SirenTile {
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[mb][r] = 0.f;
-    const float* A = L.a0;
+    const float* A = NetSmem<H>::kCache ? sm->a0 : L.a0;
 #pragma unroll
     for (int ks = 0; ks < 3; ++ks) {
       if (ks < ks0) {
@@ -213,9 +233,9 @@ struct SirenTile {
     }
   }
 
-  __device__ inline void first_layer(const DevLevel& L, float4 in, int c) {
+  __device__ inline void first_layer(const NetSmem<H>* sm, const DevLevel& L, float4 in, int c) {
     f32x16_t acc[MB];
-    layer0_acc(L, in, c, acc);
+    layer0_acc(sm, L, in, c, acc);
     activate(acc, c, true);
   }
 
@@ -231,7 +251,15 @@ struct SirenTile {
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[mb][r] = primal ? bias[acc_slot(mb, g, r)] : 0.f;
-    const char* base = (const char*)L.ah + (long long)(layer - 1) * L.ah_stride;
+    if (NetSmem<H>::kCache && layer == 1)
+      hidden_gemm((const char*)sm->ah1, acc);  // LDS
+    else
+      hidden_gemm((const char*)L.ah + (long long)(layer - 1) * L.ah_stride, acc);
+  }
+
+  // acc += A act for one hidden layer, A read from `base` (global memory or LDS).
+  __device__ inline void hidden_gemm(const char* base, f32x16_t* acc) {
+    const int lane = threadIdx.x & 63;
     if constexpr (P == PREC_FP32) {
       gemm_fp32<H>(act, (const f32x4_t*)base, acc);
     } else {
@@ -294,7 +322,7 @@ struct SirenTile {
   // dN/dx_{c-1} for c = 1..3.
   __device__ inline float eval(const NetSmem<H>* sm, const DevLevel& L, float4 in, int c) {
     NNM_MEM_FENCE();
-    first_layer(L, in, c);
+    first_layer(sm, L, in, c);
     for (int layer = 1; layer < L.n_sine; ++layer) hidden_layer(sm, L, layer, c);
     return output(sm, L, c);
   }
