@@ -107,7 +107,7 @@ def run_form(scene, precision, o, v, t, steps, warmup, final_level=-1, normal_le
                         "avg_ms": avg_ms,
                         "evals": units, "hidden_flops": flops,
                         "tflops": flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0})
-    res = {"precision": precision, "ms_per_step": ms, "rays_per_s": n / (ms * 1e-3), "hits": hits, "timing": timing,
+    res = {"precision": precision, "workload": scene.name, "ms_per_step": ms, "rays_per_s": n / (ms * 1e-3), "hits": hits, "timing": timing,
            "evals_per_level": evals, "kernels": kernels,
            "outputs": {k: v_.cpu().numpy() for k, v_ in out.items()}}
     prof.close()
@@ -153,9 +153,13 @@ def run_fit(steps, warmup):
 HBM_PROFILE = os.path.join(ROOT, "profiles", "trace_ws_stack3_1080p_hbm.txt")
 
 
-def measured_traffic(kernel, precision):
+def measured_traffic(kernel, precision, workload="stack3_1080p"):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    profile: only for the profiled configuration (bf16 k_trace_ws on the 1080p
+    stack) and only while the kernel sources hash to the profiled build."""
     import hashlib
-    if kernel != "k_trace_ws" or precision != "bf16" or not os.path.exists(HBM_PROFILE):
+    if (kernel != "k_trace_ws" or precision != "bf16" or workload != "stack3_1080p"
+            or not os.path.exists(HBM_PROFILE)):
         return None
     fields = {}
     for line in open(HBM_PROFILE):
@@ -602,7 +606,8 @@ def roofline(form):
     dom = max(form["kernels"], key=lambda k: k["avg_ms"])
     peak = PEAK_TFLOPS[form["precision"]]
     return {"bound": "mfma", "achieved": round(dom["tflops"], 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(dom["tflops"] / peak, 5), "traffic": measured_traffic(dom["kernel"], form["precision"]),
+            "frac": round(dom["tflops"] / peak, 5),
+            "traffic": measured_traffic(dom["kernel"], form["precision"], form.get("workload", "")),
             "kernel": f"{dom['kernel']} (H={dom['width']}) level {dom['level']}",
             "avg_ms": round(dom["avg_ms"], 4), "flops_per_launch": dom["hidden_flops"]}
 
@@ -720,9 +725,11 @@ def main():
     if nnm_res:
         nnm_block = {"final_level": m - 2, "normal_level": m - 1, "forms": {}}
         if cpu is not None:
-            # oracle of the variant on every 8th row of the frame
-            rows8 = np.arange(0, scene.height, 8)
+            # oracle of the variant on every (4 x cpu-rows-every)th row of the frame
+            every8 = 4 * args.cpu_rows_every
+            rows8 = np.arange(0, scene.height, every8)
             idx8 = (rows8[:, None] * scene.width + np.arange(scene.width)[None, :]).reshape(-1)
+            log(f"oracle of the NNM variant on {idx8.size} rays (every {every8}th row) ...")
             c0 = time.perf_counter()
             ref8 = orc.trace(scene, o_np[idx8], v_np[idx8], None if t_np is None else t_np[idx8],
                              final_level=m - 2, normal_level=m - 1)
