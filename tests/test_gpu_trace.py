@@ -251,3 +251,40 @@ def test_weight_stationary_matches_streaming(precision, monkeypatch):
     assert angle_deg(ws["normal"][both], st["normal"][both]).mean() <= 0.01
     r = orc.trace(s, o, v)
     check_lowp(compare(ws, r))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_concurrent_streams_share_a_stack(precision):
+    """trace_rays calls on two streams with one stack, running at the same time,
+    give bit-identical outputs to the same calls made one after another (the
+    stack is read-only; every call has its own stream-ordered scratch)."""
+    import torch
+    import paper_2201_09147_amd as nnm
+    scene = ni.make_scene("stack3_512sq").with_size(320, 200)
+    o, v, _ = scene.rays()
+    dev = torch.device("cuda", 0)
+    stack = nnm.load_siren_stack(scene, precision, 0)
+    cut = 27_001
+    parts = [(torch.from_numpy(o[:cut]).to(dev), torch.from_numpy(v[:cut]).to(dev)),
+             (torch.from_numpy(o[cut:]).to(dev), torch.from_numpy(v[cut:]).to(dev))]
+    ref = [nnm.render(stack, oi, vi) for oi, vi in parts]
+    params = nnm.TraceParams(scene.step_scale, scene.eps, scene.far, scene.max_steps)
+
+    def alloc(n):
+        return {"depth": torch.empty(n, device=dev), "hit": torch.empty(n, dtype=torch.uint8, device=dev),
+                "normal": torch.empty((n, 3), device=dev), "steps": torch.empty((n, 3), dtype=torch.uint8, device=dev),
+                "status": torch.empty(n, dtype=torch.uint8, device=dev)}
+
+    streams = [torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)]
+    for _ in range(3):
+        outs = [alloc(oi.shape[0]) for oi, _ in parts]
+        torch.cuda.synchronize()
+        for (oi, vi), out, st in zip(parts, outs, streams):
+            with torch.cuda.stream(st):
+                nnm.trace_rays(stack, params, oi, vi, None, out["depth"], out["hit"], out["normal"], out["steps"],
+                               out["status"], stream=st)
+        torch.cuda.synchronize()
+        for out, r in zip(outs, ref):
+            for key in ("depth", "hit", "normal", "steps", "status"):
+                assert torch.equal(out[key], r[key]), key
+    stack.close()
