@@ -40,11 +40,22 @@ constexpr int kTraceCols = 32;
 constexpr int kNormalCols = 64;
 constexpr int kPipeStride = 256 + 8;  // 16-bit elements per LDS column (spreads LDS banks)
 constexpr int kParkMax = kTraceCols / 2;  // most survivors a group parks (tail compaction)
+// Tracing kernel: the control wave (role 0) computes no part of the first
+// hidden product.  Its two W_1 row blocks live in LDS and roles 1 and 2 each
+// compute one of them after their own, so the control wave's stage is the
+// control alone; role 3 takes over the control wave's first-layer block.
+#ifndef NNM_WS_CTL_NOH1
+#define NNM_WS_CTL_NOH1 1
+#endif
+constexpr int kOff0Wave = NNM_WS_CTL_NOH1 ? 3 : 1;  // tracing: the wave that computes role 0's first-layer block
 static_assert(kPipeGroups == 5, "tile t uses group t % 5: five tiles are in flight");
 static_assert(kPipeGroups * kTraceCols == kWsRaysPerBlock && kPipeGroups * kNormalCols / 4 == kWsPointsPerBlock, "slots");
 
 template <int C>
 struct PipeSmem {
+  // tracing kernel with NNM_WS_CTL_NOH1: the control wave's two W_1 row blocks
+  // (2 blocks x 16 k-steps x 64 lanes of 16-byte fragments, 32 KB)
+  uint4 w1lds[(C == 32 && NNM_WS_CTL_NOH1) ? 2 * 16 * 64 : 1];
   uint16_t act0[2][C * kPipeStride];
   uint16_t act1[2][C * kPipeStride];
   float bias[2][256];
@@ -198,6 +209,50 @@ __device__ inline void pipe_hidden(const PipeWeights<P>& W, const uint16_t* src,
 }
 
 // sin of a team-1 wave's rows into the next layer's activations.
+// One 32-row block `blk` of the first hidden product with A read from LDS
+// (W_1 rows [32 blk, 32 blk + 32)); same k order as pipe_hidden.
+template <int C, int P>
+__device__ inline void pipe_hidden_lds(const uint4* wlds, int blk, const uint16_t* src, const float* bias,
+                                       f32x16_t (&acc)[(C / 32)], const PipeLane& pl) {
+  typedef HiddenOps<P> Ops;
+  typedef typename Ops::frag_t frag_t;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int b4 = 0; b4 < 4; ++b4) {
+    const float4 b = *(const float4*)&bias[32 * blk + 8 * b4 + 4 * pl.g];
+#pragma unroll
+    for (int cb = 0; cb < (C / 32); ++cb) {
+      acc[cb][4 * b4 + 0] = b.x;
+      acc[cb][4 * b4 + 1] = b.y;
+      acc[cb][4 * b4 + 2] = b.z;
+      acc[cb][4 * b4 + 3] = b.w;
+    }
+  }
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) {
+    const frag_t a = *(const frag_t*)&wlds[(blk * 16 + ks) * 64 + lane];
+    frag_t b[(C / 32)];
+#pragma unroll
+    for (int cb = 0; cb < (C / 32); ++cb)
+      b[cb] = *(const frag_t*)&src[(32 * cb + pl.j) * kPipeStride + 16 * ks + 8 * pl.g];
+#pragma unroll
+    for (int cb = 0; cb < (C / 32); ++cb) acc[cb] = Ops::mfma(a, b[cb], acc[cb]);
+  }
+}
+
+template <int C, int P, bool TAN, bool RED>
+__device__ inline void pipe_store_blk(const f32x16_t (&acc)[(C / 32)], uint16_t* dst, int blk, const PipeLane& pl) {
+#pragma unroll
+  for (int cb = 0; cb < (C / 32); ++cb)
+#pragma unroll
+    for (int b4 = 0; b4 < 4; ++b4) {
+      uint16_t h[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[i] = PipeBits<P>::bits(pipe_act<TAN, RED>(acc[cb][4 * b4 + i], pl));
+      pipe_store4(&dst[(32 * cb + pl.j) * kPipeStride + 32 * blk + 8 * b4 + 4 * pl.g], h[0], h[1], h[2], h[3]);
+    }
+}
+
 template <int C, int P, bool TAN, bool RED>
 __device__ inline void pipe_store(const f32x16_t (&acc)[(C / 32)][2], uint16_t* dst, int tw, const PipeLane& pl) {
 #pragma unroll
@@ -246,6 +301,11 @@ __device__ inline void pipe_setup(PipeSmem<C>& sm, const DevLevel& L) {
   if (threadIdx.x < 8) sm.tlive[threadIdx.x] = 0;
   if (threadIdx.x < 2) sm.stop[threadIdx.x] = 0;
   if (threadIdx.x < 4) sm.simd_count[threadIdx.x] = 0;
+  if constexpr (C == 32 && NNM_WS_CTL_NOH1) {
+    // team 1, wave 0, row blocks 0 and 1 of W_1: the first 2 x 16 x 64 fragments of ws_ah
+    const uint4* src = (const uint4*)L.ws_ah;
+    for (int i = threadIdx.x; i < 2 * 16 * 64; i += kPipeThreads) sm.w1lds[i] = src[i];
+  }
 }
 
 // Role of this wave, 4 team + simd: the first wave that arrives on a SIMD joins
@@ -276,8 +336,17 @@ template <int C, int P, bool TAN, bool RED>
 __device__ inline void pipe_team1_hidden(PipeSmem<C>& sm, const PipeWeights<P>& W, f32x16_t (&acc)[(C / 32)][2], int s,
                                          int wave, const PipeLane& pl) {
   if (sm.tlive[(s + 7) & 7]) {
+    constexpr bool kNoH1 = C == 32 && !TAN && NNM_WS_CTL_NOH1;
+    if (kNoH1 && wave == 0) return;
     pipe_hidden<C, P>(W, sm.act0[(s + 1) & 1], (TAN && pl.c) ? sm.zeros : sm.bias[0], acc, wave & 3, pl);
     pipe_store<C, P, TAN, RED>(acc, sm.act1[(s + 1) & 1], wave & 3, pl);
+    if constexpr (kNoH1) {
+      if (wave == 1 || wave == 2) {
+        f32x16_t acc1[(C / 32)];
+        pipe_hidden_lds<C, P>(sm.w1lds, wave - 1, sm.act0[(s + 1) & 1], sm.bias[0], acc1, pl);
+        pipe_store_blk<C, P, TAN, RED>(acc1, sm.act1[(s + 1) & 1], wave - 1, pl);
+      }
+    }
   }
 }
 
@@ -287,7 +356,7 @@ __device__ inline void pipe_team1_layer0(PipeSmem<C>& sm, const PipeWeights<P>& 
                                          const PipeLane& pl) {
   if (!sm.tlive[s & 7]) return;
   if (!OFF0 || wave != 0) pipe_layer0<C, P, TAN>(W, 0, sm.xin[s & 1], sm.act0[s & 1], L.d_in, wave, pl);
-  if (OFF0 && wave == 1) pipe_layer0<C, P, TAN>(W, 1, sm.xin[s & 1], sm.act0[s & 1], L.d_in, 0, pl);
+  if (OFF0 && wave == kOff0Wave) pipe_layer0<C, P, TAN>(W, 1, sm.xin[s & 1], sm.act0[s & 1], L.d_in, 0, pl);
 }
 
 #ifndef NNM_NORMAL_L0_MODE
@@ -639,7 +708,7 @@ struct TraceCtl {
 template <int P, bool RED, bool TEAM2>
 __device__ inline void trace_body(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int wave, int lane) {
   PipeWeights<P> W;
-  W.load(A.L, wave, lane, wave, wave == 1 ? 0 : -1);  // role 1 also computes the control wave's block
+  W.load(A.L, wave, lane, wave, wave == kOff0Wave ? 0 : -1);  // this role also computes the control wave's block
   const PipeLane pl = pipe_lane<false>(lane);
   const bool ctl_wave = !TEAM2 && wave == 0;
   TraceCtl ctl;
