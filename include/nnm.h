@@ -246,6 +246,11 @@ int fit_state(nnm_fit* fit, float** params, float** adam_m, float** adam_v, int6
 /* Copies params, Adam m and v to host arrays of n_params floats (any may be
    NULL); synchronises the device.  A checkpoint together with fit_get_step. */
 int fit_read_state(nnm_fit* fit, float* params, float* adam_m, float* adam_v);
+/* Writes the current parameters as a network file (nnm_write_net_file), the
+   input of load_siren_stack after a fit (the fitted network of the torus
+   workload is rendered this way).  Synchronises the fit's device first.
+   Errors: NNM_E_INVAL, NNM_E_NOMEM, NNM_E_DEVICE, NNM_E_IO. */
+int fit_export(nnm_fit* fit, const char* path);
 /* Overwrites params, m, v from host arrays (any may be NULL); synchronous. */
 int fit_write_state(nnm_fit* fit, const float* params, const float* adam_m, const float* adam_v);
 /* Steps taken so far (Adam's t); settable for a resumed run. */
@@ -360,6 +365,13 @@ int nnm_profiler_report(nnm_profiler* prof, nnm_profile_report* out);
 int nnm_read_net_file(const char* path, int32_t* d_in, int32_t* width, int32_t* n_sine,
                       float** params_out, int64_t* n_params);
 void nnm_free(void* p);
+
+/* Writes a network file (the format above) from host float32 parameters;
+   n_params must equal nnm_param_count(d_in, width, n_sine).  The file is
+   written to path + ".tmp" and renamed, so a reader never sees a partial file.
+   Errors: NNM_E_INVAL (null, shape, count), NNM_E_IO. */
+int nnm_write_net_file(const char* path, int32_t d_in, int32_t width, int32_t n_sine, const float* params,
+                       int64_t n_params);
 
 /* Number of float32 parameters of a network shape (< 0 if unsupported). */
 int64_t nnm_param_count(int32_t d_in, int32_t width, int32_t n_sine);

@@ -45,6 +45,7 @@ from ._binding import (  # noqa: F401
     nnm_validate_stack,
     nnm_level_lipschitz_bound,
     nnm_read_net_file,
+    nnm_write_net_file,
     nnm_sync,
     render,
     levels_from_scene,

@@ -81,6 +81,8 @@ def load_library():
         "nnm_mesh_extract": ([P, c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float, c_int64, c_int64, P, P, P,
                               P], c_int),
         "nnm_read_net_file": ([ctypes.c_char_p, P, P, P, P, P], c_int),
+        "nnm_write_net_file": ([ctypes.c_char_p, c_int32, c_int32, c_int32, P, c_int64], c_int),
+        "fit_export": ([P, ctypes.c_char_p], c_int),
         "nnm_free": ([P], None),
         "nnm_param_count": ([c_int32, c_int32, c_int32], c_int64),
         "nnm_sync": ([P], c_int),
@@ -481,6 +483,13 @@ def nnm_sync(stream=None, device: int = 0):
     _check(load_library().nnm_sync(_stream_ptr(stream, device)))
 
 
+def nnm_write_net_file(path: str, d_in: int, width: int, n_sine: int, params) -> None:
+    """Write float32 host parameters as a network file (nnm_write_net_file)."""
+    flat = np.ascontiguousarray(params, dtype=np.float32).ravel()
+    _check(load_library().nnm_write_net_file(str(path).encode(), int(d_in), int(width), int(n_sine),
+                                              flat.ctypes.data_as(c_void_p), flat.size))
+
+
 def nnm_read_net_file(path: str):
     """(d_in, width, n_sine, float32 params) parsed by the library."""
     lib = load_library()
@@ -603,6 +612,10 @@ class Fit:
         out = np.empty(self.n_params, np.float32)
         _check(load_library().fit_read_state(self._h, out.ctypes.data_as(c_void_p), None, None))
         return out
+
+    def export(self, path: str) -> None:
+        """Write the current parameters as a network file (fit_export)."""
+        _check(load_library().fit_export(self._h, str(path).encode()))
 
     def state(self):
         """(params, m, v, step) as numpy arrays (synchronises): a checkpoint."""

@@ -848,6 +848,29 @@ int nnm_sync(void* stream) {
   return NNM_OK;
 }
 
+int nnm_write_net_file(const char* path, int32_t d_in, int32_t width, int32_t n_sine, const float* params,
+                       int64_t n_params) {
+  g_err.clear();
+  if (!path || !params) return fail(NNM_E_INVAL, "null path or parameters");
+  if ((d_in != 3 && d_in != 4) || width < 1 || width > 4096 || n_sine < 1 || n_sine > kMaxSine)
+    return fail(NNM_E_INVAL, "shape d_in %d width %d n_sine %d", d_in, width, n_sine);
+  if (n_params != param_count(d_in, width, n_sine))
+    return fail(NNM_E_INVAL, "%lld parameters, expected %lld", (long long)n_params,
+                (long long)param_count(d_in, width, n_sine));
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* fh = std::fopen(tmp.c_str(), "wb");
+  if (!fh) return fail(NNM_E_IO, "cannot open %s", tmp.c_str());
+  const uint32_t hdr[7] = {1u, (uint32_t)d_in, (uint32_t)width, (uint32_t)n_sine, 0u, 0u, 0u};
+  bool ok = std::fwrite("NNMW", 1, 4, fh) == 4 && std::fwrite(hdr, 4, 7, fh) == 7 &&
+            std::fwrite(params, 4, (size_t)n_params, fh) == (size_t)n_params;
+  ok = (std::fclose(fh) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return fail(NNM_E_IO, "cannot write %s", path);
+  }
+  return NNM_OK;
+}
+
 int nnm_read_net_file(const char* path, int32_t* d_in, int32_t* width, int32_t* n_sine, float** params_out,
                       int64_t* n_params) {
   g_err.clear();
@@ -1291,6 +1314,20 @@ int fit_state(nnm_fit* f, float** params, float** adam_m, float** adam_v, int64_
   if (adam_v) *adam_v = f->state + 2 * f->n_params;
   if (n_params) *n_params = f->n_params;
   return NNM_OK;
+}
+
+int fit_export(nnm_fit* f, const char* path) {
+  g_err.clear();
+  if (!f || !path) return fail(NNM_E_INVAL, "null fit or path");
+  std::vector<float> host;
+  try {
+    host.resize((size_t)f->n_params);
+  } catch (...) {
+    return fail(NNM_E_NOMEM, "host buffer");
+  }
+  int rc = fit_read_state(f, host.data(), nullptr, nullptr);
+  if (rc != NNM_OK) return rc;
+  return nnm_write_net_file(path, f->shape.d_in, f->shape.width, f->shape.n_sine, host.data(), f->n_params);
 }
 
 int fit_read_state(nnm_fit* f, float* params, float* adam_m, float* adam_v) {

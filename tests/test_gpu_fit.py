@@ -132,6 +132,33 @@ def test_checkpoint_resume_is_bitwise():
     del torch
 
 
+def test_fit_export_writes_a_loadable_network(tmp_path):
+    """fit_export after a few steps: the file holds exactly the fit's parameters,
+    and a stack loaded from it evaluates the fitted network (against the oracle)."""
+    import torch
+    net = ni.siren_init(6, 3, 64, 2, 1.0, normalise=False)
+    fit = _fit(net, 2048)
+    for s in range(3):
+        fit.step_adam(*(_t(a) for a in _batch(256, 1024, s)), lr=1e-3)
+    path = tmp_path / "fitted.nnmw"
+    fit.export(str(path))
+    d_in, width, n_sine, params = nnm.nnm_read_net_file(str(path))
+    assert (d_in, width, n_sine) == (3, 64, 2)
+    assert np.array_equal(params, fit.params())
+    fitted = ni.read_net_file(str(path))
+    spec = nnm.LevelSpec(d_in, width, n_sine, params, 1.0, 0.0)
+    stack = nnm.load_siren_stack([spec], "fp32", 0, base_sphere=False, lipschitz_max=0.0)
+    x = np.random.default_rng(1).uniform(-1, 1, size=(1000, 3)).astype(np.float32)
+    val = torch.empty(1000, device=_dev())
+    nnm.nnm_net_eval(stack, 0, _t(x), None, val, None)
+    torch.cuda.synchronize()
+    from oracle import tracing as orc
+    ref = orc.net_eval(fitted, x.astype(np.float64), grad=False)
+    assert np.abs(val.cpu().numpy() - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+    stack.close()
+    fit.close()
+
+
 def test_autograd_function_matches_torch_double_backward():
     import torch
     from paper_2201_09147_amd.autograd import siren

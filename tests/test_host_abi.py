@@ -147,3 +147,27 @@ def test_mesh_entry_points_reject_bad_arguments_before_device_use(lib):
     assert ext(fake, 8, f(-1), f(1), f(0), 0, 4, fake, None, fake, None) == -1
     assert lib.nnm_grid_values(None, 0, 8, f(-1), f(1), f(0), fake, None) == -1
     assert lib.neural_normal_map(None, 0, 4, fake, None, fake, None) == -1
+
+
+def test_write_net_file_roundtrip_and_errors(lib, tmp_path):
+    """nnm_write_net_file writes what nnm_read_net_file and the input module's
+    reader read back; shape and count errors fail before writing."""
+    net = ni.make_scene("stack3_512sq").levels[1].net
+    flat = net.flat()
+    p = tmp_path / "w.nnmw"
+    nnm.nnm_write_net_file(str(p), net.d_in, net.width, net.n_sine, flat)
+    d_in, width, n_sine, params = nnm.nnm_read_net_file(str(p))
+    assert (d_in, width, n_sine) == (net.d_in, net.width, net.n_sine)
+    assert np.array_equal(params, flat)
+    back = ni.read_net_file(str(p))
+    assert np.array_equal(back.flat(), flat)
+    assert not (tmp_path / "w.nnmw.tmp").exists()
+    with pytest.raises(nnm.NnmError) as e:
+        nnm.nnm_write_net_file(str(tmp_path / "bad.nnmw"), net.d_in, net.width, net.n_sine, flat[:-1])
+    assert e.value.code == -1
+    with pytest.raises(nnm.NnmError):
+        nnm.nnm_write_net_file(str(tmp_path / "bad.nnmw"), 5, net.width, net.n_sine, flat)
+    with pytest.raises(nnm.NnmError) as e:
+        nnm.nnm_write_net_file(str(tmp_path / "no_such_dir" / "x.nnmw"), net.d_in, net.width, net.n_sine, flat)
+    assert e.value.code == -9
+    assert not (tmp_path / "bad.nnmw").exists()
