@@ -91,14 +91,18 @@ __global__ void k_fit_pack(FitPackArgs A) {
   }
 }
 
-// --------------------------------------------------------- fused fwd + bwd
-template <int H>
+// ------------------------------------------------ forward, then reverse
+// Two launches over the same tile-to-wave map: FWD runs the forward pass and
+// the loss adjoints (written to adj), the reverse launch starts from adj.  As
+// one kernel the two phases' register states overlap and spill.
+template <int H, bool FWD>
 __global__ void __launch_bounds__(kBlockThreads) k_fit_fb(FitArgs A) {
   constexpr int MB = H / 32;
   __shared__ NetSmem<H> sm;
-  __shared__ float4 s_w0t[H];
+  __shared__ float4 s_w0t[FWD ? 1 : H];
   stage_net<H>(&sm, A.L);
-  for (int i = threadIdx.x; i < H; i += blockDim.x) s_w0t[i] = A.w0t[i];
+  if (!FWD)
+    for (int i = threadIdx.x; i < H; i += blockDim.x) s_w0t[i] = A.w0t[i];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int col = lane & 31;
@@ -116,6 +120,7 @@ __global__ void __launch_bounds__(kBlockThreads) k_fit_fb(FitArgs A) {
     const int p = t * 8 + q;
     const bool live = p < A.n;
     const long long gcol = (long long)t * 32 + col;
+    if constexpr (FWD) {
     // ---- inputs
     const float* xp = nullptr;
     bool surf = false;
@@ -135,11 +140,15 @@ __global__ void __launch_bounds__(kBlockThreads) k_fit_fb(FitArgs A) {
       if (A.L.d_in == 4) in.w = xp[3];
     }
     // ---- forward: store pre-activations (revolutions) and layer inputs
-    f32x16_t acc[MB];
     NNM_MEM_FENCE();
-    tile.layer0_acc(&sm, A.L, in, c, acc);
     for (int layer = 0; layer < K; ++layer) {
-      if (layer > 0) tile.hidden_acc(&sm, A.L, layer, c, acc);
+      // acc is born inside the iteration: live across the back edge are only
+      // the activations, which keeps the forward within the register file.
+      f32x16_t acc[MB];
+      if (layer == 0)
+        tile.layer0_acc(&sm, A.L, in, c, acc);
+      else
+        tile.hidden_acc(&sm, A.L, layer, c, acc);
       // [column][neuron] slabs: rows 32 mb + 8 b + 4 g .. +3 are 16 contiguous bytes
       float4* pa = (float4*)(A.ws_abar + ((long long)layer * Kc + gcol) * H + 4 * g);
 #pragma unroll
@@ -204,7 +213,9 @@ __global__ void __launch_bounds__(kBlockThreads) k_fit_fb(FitArgs A) {
     }
     const float adjc = (c == 0) ? Nbar : (c == 1 ? gb[0] : (c == 2 ? gb[1] : gb[2]));
     if (g == 0) A.adj[gcol] = adjc;
+    } else {
     // ---- reverse: X-bar of the output layer, then layer by layer
+    const float adjc = A.adj[gcol];
     NNM_MEM_FENCE();
     float xbar[MB][16];
 #pragma unroll
@@ -272,9 +283,10 @@ __global__ void __launch_bounds__(kBlockThreads) k_fit_fb(FitArgs A) {
           for (int j = 0; j < A.L.d_in; ++j) A.dx[(long long)A.L.d_in * p + j] = d4[j];
       }
     }
+    }
   }
   // per-wave loss partial sums (deterministic: fixed tile to wave map)
-  if (A.loss_part) {
+  if (FWD && A.loss_part) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       float v = lsum[j];
@@ -354,97 +366,184 @@ __global__ void k_adam(float* params, const float* grad, float* m, float* v, lon
 }
 
 // ------------------------------------------- weight-gradient reductions
-// Column reduction over a [Kc][H] slab: part[chunk][r][row] =
-// sum_{col in chunk} M[col][row] w_r[col] for R column-weight vectors (stride Kc).
+// Column reduction over a [Kc][H] slab, restricted to the columns
+// col = j * cstep (a weight vector that vanishes elsewhere by construction,
+// such as the primal mask, lets the other columns go unread).  First pass:
+// block b takes the stepped columns j in [b * per_blk, (b + 1) * per_blk) and
+// writes part[b][r][row] = sum_j M[j cstep][row] w_r[j cstep].  A thread owns
+// four consecutive rows of one column (one 16-byte load); the block covers
+// 1024 / H columns per pass and keeps kColU passes of loads in flight.  The
+// per-thread sums are combined in LDS in a fixed order, so results do not
+// depend on scheduling.
+constexpr int kColU = 8;
 template <int R>
 __global__ void __launch_bounds__(256) k_colreduce(const float* __restrict__ M, int H, long long Kc,
-                                                   const float* __restrict__ w, int chunk, float* __restrict__ part) {
-  const int row = threadIdx.x;
-  if (row >= H) return;
-  const long long c0 = (long long)blockIdx.x * chunk;
-  const long long c1 = min(c0 + chunk, Kc);
-  float acc[R];
+                                                   const float* __restrict__ w, int cstep, long long per_blk,
+                                                   float* __restrict__ part) {
+  __shared__ float4 sh[R][256];  // [r][sub * H / 4 + q]
+  const int tid = threadIdx.x;
+  const int lq = H >> 2;         // threads per column
+  const int cpi = 256 / lq;      // columns per block pass
+  const int sub = tid / lq, q = tid - sub * lq;
+  const long long nsc = (Kc + cstep - 1) / cstep;
+  const long long j0 = (long long)blockIdx.x * per_blk;
+  const long long j1 = min(j0 + per_blk, nsc);
+  float4 acc[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = 0.f;
-  for (long long col = c0; col < c1; ++col) {
-    const float m = M[col * H + row];
+  for (int r = 0; r < R; ++r) acc[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4* M4 = reinterpret_cast<const float4*>(M);
+  long long j = j0 + sub;
+  for (; j + (long long)(kColU - 1) * cpi < j1; j += (long long)kColU * cpi) {
+    float4 m[kColU];
+    float wv[kColU][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = fmaf(m, w[r * Kc + col], acc[r]);
+    for (int u = 0; u < kColU; ++u) {
+      const long long col = (j + (long long)u * cpi) * cstep;
+      m[u] = M4[col * lq + q];
+#pragma unroll
+      for (int r = 0; r < R; ++r) wv[u][r] = w[r * Kc + col];
+    }
+#pragma unroll
+    for (int u = 0; u < kColU; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        acc[r].x = fmaf(m[u].x, wv[u][r], acc[r].x);
+        acc[r].y = fmaf(m[u].y, wv[u][r], acc[r].y);
+        acc[r].z = fmaf(m[u].z, wv[u][r], acc[r].z);
+        acc[r].w = fmaf(m[u].w, wv[u][r], acc[r].w);
+      }
+  }
+  for (; j < j1; j += cpi) {
+    const long long col = j * cstep;
+    const float4 m = M4[col * lq + q];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float wr = w[r * Kc + col];
+      acc[r].x = fmaf(m.x, wr, acc[r].x);
+      acc[r].y = fmaf(m.y, wr, acc[r].y);
+      acc[r].z = fmaf(m.z, wr, acc[r].z);
+      acc[r].w = fmaf(m.w, wr, acc[r].w);
+    }
   }
 #pragma unroll
-  for (int r = 0; r < R; ++r) part[((long long)blockIdx.x * R + r) * H + row] = acc[r];
+  for (int r = 0; r < R; ++r) sh[r][tid] = acc[r];
+  __syncthreads();
+  const float* shf = reinterpret_cast<const float*>(&sh[0][0]);
+  for (int o = tid; o < R * H; o += 256) {
+    const int r = o / H, row = o - r * H;
+    float s = 0.f;
+    for (int c = 0; c < cpi; ++c) s += shf[r * 1024 + c * H + row];
+    part[((long long)blockIdx.x * R + r) * H + row] = s;
+  }
 }
 
-// dst_r[row * stride_r] = sum over chunks (fixed order) of part[chunk][r][row].
-__global__ void k_colreduce_final(const float* __restrict__ part, int nchunk, int R, int H, ColDst dst) {
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+// Second pass: dst_r[row * stride_r] = sum over the nblk first-pass blocks of
+// part[b][r][row].  Block (64 rows) x (16 interleaved groups of blocks); the
+// groups are added in a fixed order.
+__global__ void __launch_bounds__(1024) k_colreduce_final(const float* __restrict__ part, int nblk, int R, int H,
+                                                          ColDst dst) {
+  __shared__ float sh[16][64];
+  const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
+  const int row = blockIdx.x * 64 + x;
   const int r = blockIdx.y;
-  if (row >= H) return;
   float s = 0.f;
-  for (int c = 0; c < nchunk; ++c) s += part[((long long)c * R + r) * H + row];
-  dst.ptr[r][(long long)row * dst.stride[r]] = s;
+  if (row < H) {
+#pragma unroll 8
+    for (int c = y; c < nblk; c += 16) s += part[((long long)c * R + r) * H + row];
+  }
+  sh[y][x] = s;
+  __syncthreads();
+  if (y == 0 && row < H) {
+    float t = 0.f;
+#pragma unroll
+    for (int g = 0; g < 16; ++g) t += sh[g][x];
+    dst.ptr[r][(long long)row * dst.stride[r]] = t;
+  }
 }
 
 // Weight gradient of a hidden layer, split over column chunks:
 // part[chunk][o][i] = sum_{col in chunk} abar[col][o] X[col][i] (32x32x2 fp32
-// MFMAs; wave w accumulates row blocks w, w+4, ... against every column block).
+// MFMAs).  One wave per 32-row block of the output, each accumulating against
+// every 32-column block (H/32 accumulator tiles: two waves fit a SIMD at
+// H = 256, so one loads while the other multiplies).  Each iteration issues
+// all loads of kWgradU column pairs before the first of their MFMAs (left to
+// itself the scheduler spreads the loads between the MFMAs, and the late ones
+// expose their latency).
+constexpr int kWgradU = 4;
 template <int H>
-__global__ void __launch_bounds__(256) k_wgrad(const float* __restrict__ abar, const float* __restrict__ X,
-                                               long long Kc, int chunk, float* __restrict__ part) {
+__global__ void __launch_bounds__(2 * H) k_wgrad(const float* __restrict__ abar, const float* __restrict__ X,
+                                                 long long Kc, int chunk, float* __restrict__ part) {
   constexpr int MB = H / 32;
-  constexpr int RPW = MB >= 4 ? MB / 4 : 1;  // row blocks per wave
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 31, g = lane >> 5;
-  if (wave >= MB) return;  // small widths: fewer row blocks than waves
-  f32x16_t acc[RPW][MB];
+  f32x16_t acc[MB];
 #pragma unroll
-  for (int a = 0; a < RPW; ++a)
+  for (int b = 0; b < MB; ++b)
 #pragma unroll
-    for (int b = 0; b < MB; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+    for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
   const long long c0 = (long long)blockIdx.x * chunk;
   const long long c1 = min(c0 + chunk, Kc);
-  for (long long col = c0; col < c1; col += 2) {
-    const long long cg = col + g;
-    const bool ok = cg < c1;
-    float av[RPW], bv[MB];
+  // Kc and chunk are multiples of 2 kWgradU, so every batch is whole.
+  for (long long col = c0; col < c1; col += 2 * kWgradU) {
+    float av[kWgradU], bv[kWgradU][MB];
 #pragma unroll
-    for (int a = 0; a < RPW; ++a) av[a] = ok ? abar[cg * H + 32 * (wave + 4 * a) + i] : 0.f;
+    for (int u = 0; u < kWgradU; ++u) {
+      const long long cg = col + 2 * u + g;
+      av[u] = abar[cg * H + 32 * wave + i];
 #pragma unroll
-    for (int b = 0; b < MB; ++b) bv[b] = ok ? X[cg * H + 32 * b + i] : 0.f;
+      for (int b = 0; b < MB; ++b) bv[u][b] = X[cg * H + 32 * b + i];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // every load of the batch issues before the first MFMA
 #pragma unroll
-    for (int a = 0; a < RPW; ++a)
+    for (int u = 0; u < kWgradU; ++u)
 #pragma unroll
-      for (int b = 0; b < MB; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+      for (int b = 0; b < MB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u][b], acc[b], 0, 0, 0);
   }
   float* out = part + (long long)blockIdx.x * H * H;
 #pragma unroll
-  for (int a = 0; a < RPW; ++a)
+  for (int b = 0; b < MB; ++b)
 #pragma unroll
-    for (int b = 0; b < MB; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int o = 32 * (wave + 4 * a) + 8 * (r / 4) + 4 * g + (r % 4);
-        out[(long long)o * H + 32 * b + i] = acc[a][b][r];
-      }
+    for (int r = 0; r < 16; ++r) {
+      const int o = 32 * wave + 8 * (r / 4) + 4 * g + (r % 4);
+      out[(long long)o * H + 32 * b + i] = acc[b][r];
+    }
 }
 
 __global__ void k_wgrad_final(const float* __restrict__ part, int nchunk, long long HH, float* __restrict__ dst) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < HH; e += (long long)gridDim.x * blockDim.x) {
     float s = 0.f;
+#pragma unroll 8
     for (int c = 0; c < nchunk; ++c) s += part[(long long)c * HH + e];
     dst[e] = s;
   }
 }
 
-// Sum of adj[col] mask[col] over all columns (one block, fixed order).
-__global__ void k_masked_sum(const float* __restrict__ a, const float* __restrict__ m, long long n, float* out) {
+// Sum of a[j cstep] m[j cstep] over the stepped columns: block b sums the range
+// [b per_blk, (b + 1) per_blk) into part[b] (fixed-order tree), then one block
+// adds the partial sums in a fixed order.
+__global__ void __launch_bounds__(256) k_masked_sum(const float* __restrict__ a, const float* __restrict__ m,
+                                                    long long n, int cstep, long long per_blk,
+                                                    float* __restrict__ part) {
   __shared__ float sh[256];
+  const long long nsc = (n + cstep - 1) / cstep;
+  const long long j0 = (long long)blockIdx.x * per_blk, j1 = min(j0 + per_blk, nsc);
   float s = 0.f;
-  for (long long e = threadIdx.x; e < n; e += blockDim.x) s = fmaf(a[e], m[e], s);
+  for (long long j = j0 + threadIdx.x; j < j1; j += 256) s = fmaf(a[j * cstep], m[j * cstep], s);
   sh[threadIdx.x] = s;
   __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_sum_final(const float* __restrict__ part, int nblk, float* out) {
+  __shared__ float sh[256];
+  float s = 0.f;
+  for (int b = threadIdx.x; b < nblk; b += 256) s += part[b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
     __syncthreads();
   }
@@ -453,30 +552,46 @@ __global__ void k_masked_sum(const float* __restrict__ a, const float* __restric
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_colreduce(const float* M, int H, long long Kc, const float* w, int R, int chunk, float* part,
+int colreduce_blocks(long long ncols, int H) {
+  const long long cpi = 1024 / H;
+  return (int)std::max<long long>(1, std::min<long long>(kColBlocks, (ncols + cpi - 1) / cpi));
+}
+
+hipError_t launch_colreduce(const float* M, int H, long long Kc, const float* w, int R, int cstep, float* part,
                             const ColDst& dst, hipStream_t s) {
-  const int nchunk = (int)((Kc + chunk - 1) / chunk);
+  if (H < 32 || H > 256 || (H & 31) || cstep < 1 || Kc < 1) return hipErrorInvalidValue;
+  const long long nsc = (Kc + cstep - 1) / cstep;
+  int nblk = colreduce_blocks(nsc, H);
+  const long long per_blk = (nsc + nblk - 1) / nblk;
+  nblk = (int)((nsc + per_blk - 1) / per_blk);
   switch (R) {
-    case 1: hipLaunchKernelGGL(k_colreduce<1>, dim3(nchunk), dim3(256), 0, s, M, H, Kc, w, chunk, part); break;
-    case 2: hipLaunchKernelGGL(k_colreduce<2>, dim3(nchunk), dim3(256), 0, s, M, H, Kc, w, chunk, part); break;
-    case 4: hipLaunchKernelGGL(k_colreduce<4>, dim3(nchunk), dim3(256), 0, s, M, H, Kc, w, chunk, part); break;
-    case 5: hipLaunchKernelGGL(k_colreduce<5>, dim3(nchunk), dim3(256), 0, s, M, H, Kc, w, chunk, part); break;
+#define NNM_COLRED(RR)                                                                                       \
+  case RR:                                                                                                  \
+    hipLaunchKernelGGL(k_colreduce<RR>, dim3(nblk), dim3(256), 0, s, M, H, Kc, w, cstep, per_blk, part); \
+    break;
+    NNM_COLRED(1)
+    NNM_COLRED(2)
+    NNM_COLRED(4)
+    NNM_COLRED(5)
+#undef NNM_COLRED
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_colreduce_final, dim3((H + 255) / 256, R), dim3(256), 0, s, part, nchunk, R, H, dst);
+  hipLaunchKernelGGL(k_colreduce_final, dim3((H + 63) / 64, R), dim3(1024), 0, s, part, nblk, R, H, dst);
   return hipGetLastError();
 }
 
 hipError_t launch_wgrad(int H, const float* abar, const float* X, long long Kc, int chunk, float* part, float* dst,
                         hipStream_t s) {
+  constexpr int kStep = 2 * kWgradU;
+  if (Kc % kStep || chunk % kStep || chunk < kStep || Kc < kStep) return hipErrorInvalidValue;
   const int nchunk = (int)((Kc + chunk - 1) / chunk);
   switch (H) {
-    case 32: hipLaunchKernelGGL(k_wgrad<32>, dim3(nchunk), dim3(256), 0, s, abar, X, Kc, chunk, part); break;
-    case 64: hipLaunchKernelGGL(k_wgrad<64>, dim3(nchunk), dim3(256), 0, s, abar, X, Kc, chunk, part); break;
+    case 32: hipLaunchKernelGGL(k_wgrad<32>, dim3(nchunk), dim3(64), 0, s, abar, X, Kc, chunk, part); break;
+    case 64: hipLaunchKernelGGL(k_wgrad<64>, dim3(nchunk), dim3(128), 0, s, abar, X, Kc, chunk, part); break;
     case 128: hipLaunchKernelGGL(k_wgrad<128>, dim3(nchunk), dim3(256), 0, s, abar, X, Kc, chunk, part); break;
-    case 256: hipLaunchKernelGGL(k_wgrad<256>, dim3(nchunk), dim3(256), 0, s, abar, X, Kc, chunk, part); break;
+    case 256: hipLaunchKernelGGL(k_wgrad<256>, dim3(nchunk), dim3(512), 0, s, abar, X, Kc, chunk, part); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
@@ -487,8 +602,17 @@ hipError_t launch_wgrad(int H, const float* abar, const float* X, long long Kc, 
   return hipGetLastError();
 }
 
-hipError_t launch_masked_sum(const float* a, const float* m, long long n, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_masked_sum, dim3(1), dim3(256), 0, s, a, m, n, out);
+hipError_t launch_masked_sum(const float* a, const float* m, long long n, int cstep, float* part, float* out,
+                             hipStream_t s) {
+  if (cstep < 1 || n < 1) return hipErrorInvalidValue;
+  const long long nsc = (n + cstep - 1) / cstep;
+  int nblk = (int)std::min<long long>(kSumBlocks, (nsc + 255) / 256);
+  const long long per_blk = (nsc + nblk - 1) / nblk;
+  nblk = (int)((nsc + per_blk - 1) / per_blk);
+  hipLaunchKernelGGL(k_masked_sum, dim3(nblk), dim3(256), 0, s, a, m, n, cstep, per_blk, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, part, nblk, out);
   return hipGetLastError();
 }
 
@@ -502,13 +626,20 @@ hipError_t launch_fit_pack(const FitPackArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_fit_fb(const FitArgs& a, int grid, hipStream_t s) {
+#define NNM_FIT_FB(HH)                                                                    \
+  case HH:                                                                                \
+    hipLaunchKernelGGL((k_fit_fb<HH, true>), dim3(grid), dim3(kBlockThreads), 0, s, a);  \
+    if (hipGetLastError() != hipSuccess) break;                                           \
+    hipLaunchKernelGGL((k_fit_fb<HH, false>), dim3(grid), dim3(kBlockThreads), 0, s, a); \
+    break;
   switch (a.L.width) {
-    case 32: hipLaunchKernelGGL(k_fit_fb<32>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
-    case 64: hipLaunchKernelGGL(k_fit_fb<64>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
-    case 128: hipLaunchKernelGGL(k_fit_fb<128>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
-    case 256: hipLaunchKernelGGL(k_fit_fb<256>, dim3(grid), dim3(kBlockThreads), 0, s, a); break;
+    NNM_FIT_FB(32)
+    NNM_FIT_FB(64)
+    NNM_FIT_FB(128)
+    NNM_FIT_FB(256)
     default: return hipErrorInvalidValue;
   }
+#undef NNM_FIT_FB
   return hipGetLastError();
 }
 
@@ -533,10 +664,12 @@ hipError_t launch_adam(float* params, const float* grad, float* m, float* v, lon
 }
 
 int fit_fb_grid(int width, int device) {
-  const void* fn = width == 32 ? (const void*)k_fit_fb<32>
-                   : width == 64 ? (const void*)k_fit_fb<64>
-                   : width == 128 ? (const void*)k_fit_fb<128>
-                                  : (const void*)k_fit_fb<256>;
+  // both phases use the grid of the forward launch (the loss partial sums
+  // are laid out per wave of that grid)
+  const void* fn = width == 32 ? (const void*)k_fit_fb<32, true>
+                   : width == 64 ? (const void*)k_fit_fb<64, true>
+                   : width == 128 ? (const void*)k_fit_fb<128, true>
+                                  : (const void*)k_fit_fb<256, true>;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlockThreads, 0) != hipSuccess || per_cu < 1)
     per_cu = 1;

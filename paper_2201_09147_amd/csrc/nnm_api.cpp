@@ -937,8 +937,8 @@ struct FitLayout {
   int nwaves = 0;
   size_t off_a0, off_bh, off_wk, off_bk, off_ah, off_aht, off_w0t;
   size_t off_abar, off_x, off_adj, off_mask, off_wvec, off_loss, off_part;
-  long long chunk_c = 0, chunk_w = 0;
-  int nchunk_c = 0, nchunk_w = 0;
+  long long chunk_w = 0;
+  int nchunk_w = 0;
   size_t total;
 };
 
@@ -969,11 +969,10 @@ FitLayout fit_layout(const nnm_net_shape& sh, int64_t n, int grid) {
   L.off_wvec = L.off_mask + (size_t)L.Kc * 4;
   L.off_loss = take((size_t)L.nwaves * 16 + 16);
   // partial sums of the weight-gradient reductions (used one after another)
-  L.chunk_c = 2048;
-  L.nchunk_c = (int)((L.Kc + L.chunk_c - 1) / L.chunk_c);
-  L.chunk_w = std::max(64LL, ((L.Kc + 255) / 256 + 1) & ~1LL);
+  L.chunk_w = std::max(64LL, ((L.Kc + 255) / 256 + 15) & ~15LL);  // whole column batches
   L.nchunk_w = (int)((L.Kc + L.chunk_w - 1) / L.chunk_w);
-  L.off_part = take(std::max((size_t)L.nchunk_c * 5 * H, (size_t)L.nchunk_w * H * H) * 4);
+  const size_t col_part = (size_t)colreduce_blocks(L.Kc, (int)H) * 5 * H;
+  L.off_part = take(std::max({col_part, (size_t)L.nchunk_w * H * H, (size_t)kSumBlocks}) * 4);
   L.total = o;
   return L;
 }
@@ -1068,6 +1067,8 @@ int fit_backward_impl(const nnm_net_shape& sh, const float* params, int device, 
   }
   // layer 0: b_0-bar (primal mask) and W_0-bar[:, j] (column weights w_j); the
   // mask and the w_j are contiguous vectors of length Kc in the workspace.
+  // Point p owns columns 4p (primal) .. 4p+3 (tangents), so a reduction
+  // weighted by the primal mask alone reads every fourth column.
   {
     ColDst dst{};
     dst.ptr[0] = dparams + pk.b_off[0];
@@ -1076,24 +1077,24 @@ int fit_backward_impl(const nnm_net_shape& sh, const float* params, int device, 
       dst.ptr[1 + j] = dparams + pk.w_off[0] + j;
       dst.stride[1 + j] = d_in;
     }
-    if ((e = launch_colreduce(abar, H, FL.Kc, va.mask, 1 + d_in, (int)FL.chunk_c, part, dst, st)) != hipSuccess)
+    if ((e = launch_colreduce(abar, H, FL.Kc, va.mask, 1 + d_in, 1, part, dst, st)) != hipSuccess)
       return hip_fail(e, "first-layer gradient");
   }
   for (int i = 1; i < K; ++i) {
     ColDst dst{};
     dst.ptr[0] = dparams + pk.b_off[i];
     dst.stride[0] = 1;
-    if ((e = launch_colreduce(abar + i * LS, H, FL.Kc, va.mask, 1, (int)FL.chunk_c, part, dst, st)) != hipSuccess)
+    if ((e = launch_colreduce(abar + i * LS, H, FL.Kc, va.mask, 1, 4, part, dst, st)) != hipSuccess)
       return hip_fail(e, "bias gradient");
   }
   {
     ColDst dst{};
     dst.ptr[0] = dparams + pk.w_off[K];
     dst.stride[0] = 1;
-    if ((e = launch_colreduce(X + (K - 1) * LS, H, FL.Kc, a.adj, 1, (int)FL.chunk_c, part, dst, st)) != hipSuccess)
+    if ((e = launch_colreduce(X + (K - 1) * LS, H, FL.Kc, a.adj, 1, 1, part, dst, st)) != hipSuccess)
       return hip_fail(e, "output-layer gradient");
   }
-  if ((e = launch_masked_sum(a.adj, va.mask, FL.Kc, dparams + pk.b_off[K], st)) != hipSuccess)
+  if ((e = launch_masked_sum(a.adj, va.mask, FL.Kc, 4, part, dparams + pk.b_off[K], st)) != hipSuccess)
     return hip_fail(e, "output-bias gradient");
   return NNM_OK;
 }

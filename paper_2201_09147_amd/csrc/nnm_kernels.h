@@ -160,11 +160,18 @@ struct ColDst {
   float* ptr[5];
   long long stride[5];
 };
-hipError_t launch_colreduce(const float* M, int H, long long Kc, const float* w, int R, int chunk, float* part,
+// Column reductions run in two passes; the first writes colreduce_blocks(.) * R * H
+// partial sums (kColBlocks * R * H at most) and the masked sum kSumBlocks.
+constexpr int kColBlocks = 1024;
+constexpr int kSumBlocks = 256;
+int colreduce_blocks(long long ncols, int H);
+// R weighted column sums of the columns col = j * cstep of a [Kc][H] slab.
+hipError_t launch_colreduce(const float* M, int H, long long Kc, const float* w, int R, int cstep, float* part,
                             const ColDst& dst, hipStream_t s);
 hipError_t launch_wgrad(int H, const float* abar, const float* X, long long Kc, int chunk, float* part, float* dst,
                         hipStream_t s);
-hipError_t launch_masked_sum(const float* a, const float* m, long long n, float* out, hipStream_t s);
+hipError_t launch_masked_sum(const float* a, const float* m, long long n, int cstep, float* part, float* out,
+                             hipStream_t s);
 
 hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
 hipError_t launch_box_points(uint64_t seed, long long base, int count, float lo, float hi, float* x, float* t,
