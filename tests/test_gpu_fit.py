@@ -62,6 +62,30 @@ def test_backward_upstream_adjoints(seed, d_in, H, K):
     assert rel_l2(dx.cpu().numpy(), rdx) <= 1e-4
 
 
+@pytest.mark.parametrize("seed,d_in,H,K,n", [(3, 3, 32, 2, 1), (5, 3, 32, 2, 37), (7, 3, 64, 2, 5),
+                                              (8, 3, 128, 3, 999), (9, 4, 256, 2, 300)])
+def test_backward_per_parameter_block(seed, d_in, H, K, n):
+    """Every weight and bias block on its own (the whole-vector norm is dominated
+    by the output weights), at every width, down to a single point (one column
+    tile), with ragged batch sizes."""
+    import torch
+    net = ni.siren_init(seed, d_in, H, K, 1.0, normalise=False)
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1, 1, size=(n, d_in)).astype(np.float32)
+    dv = rng.normal(size=n).astype(np.float32)
+    dg = rng.normal(size=(n, 3)).astype(np.float32)
+    dx = torch.empty((n, d_in), dtype=torch.float32, device=_dev())
+    dp, dx = nnm.siren_backward(d_in, H, K, _t(net.flat()), _t(x), _t(dv), _t(dg), dx=dx)
+    grads, rdx = F.backward(net.layers, x.astype(np.float64), dv.astype(np.float64), dg.astype(np.float64))
+    got = ni.unflatten_params(dp.cpu().numpy().astype(np.float64), d_in, H, K)
+    ref = ni.unflatten_params(F.flatten_grads(grads), d_in, H, K)
+    for i, ((gw, gb), (rw, rb)) in enumerate(zip(got, ref)):
+        ew, eb = rel_l2(gw, rw), rel_l2(gb, rb)
+        print(f"H={H} K={K} n={n} layer {i}: rel L2 W {ew:.2e}, b {eb:.2e}")
+        assert ew <= 1e-4 and eb <= 1e-4, (i, ew, eb)
+    assert rel_l2(dx.cpu().numpy(), rdx) <= 1e-4
+
+
 def _fit(net, max_points):
     return nnm.Fit(net.d_in, net.width, net.n_sine, net.flat(), 0, max_points)
 
@@ -80,6 +104,10 @@ def test_loss_and_gradient(ns, nu):
     e = rel_l2(dp.cpu().numpy(), F.flatten_grads(grads))
     print(f"loss+grad ns={ns} nu={nu}: rel L2 {e:.2e}")
     assert e <= 1e-4
+    got = ni.unflatten_params(dp.cpu().numpy().astype(np.float64), 3, 256, 3)
+    ref = ni.unflatten_params(F.flatten_grads(grads), 3, 256, 3)
+    for i, ((gw, gb), (rw, rb)) in enumerate(zip(got, ref)):
+        assert rel_l2(gw, rw) <= 1e-4 and rel_l2(gb, rb) <= 1e-4, i
     fit.close()
 
 
