@@ -91,6 +91,9 @@ __global__ void k_fit_pack(FitPackArgs A) {
   }
 }
 
+#ifndef NNM_FIT_BWD_PRE
+#define NNM_FIT_BWD_PRE 4
+#endif
 // ------------------------------------------------ forward, then reverse
 // Two launches over the same tile-to-wave map: FWD runs the forward pass and
 // the loss adjoints (written to adj), the reverse launch starts from adj.  As
@@ -226,11 +229,24 @@ __global__ void __launch_bounds__(kBlockThreads) k_fit_fb(FitArgs A) {
       float4* pa = (float4*)(A.ws_abar + ((long long)layer * Kc + gcol) * H + 4 * g);
       const bool reduce = layer == 0 || A.L.reduce_hidden;
       NNM_MEM_FENCE();
+      // Slab loads run kPre row blocks ahead of their use at H = 256 (a single
+      // wave per SIMD hides no latency by itself; narrower widths run two or
+      // more waves per SIMD and load at the point of use).
+      constexpr int kPre = H >= 256 ? NNM_FIT_BWD_PRE : 0;
+      float4 pv[MB][4];  // primal: a / 2pi; tangent: dA / 2pi
+#pragma unroll
+      for (int mb = 0; mb < kPre; ++mb)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) pv[mb][b] = pa[(32 * mb + 8 * b) / 4];
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
+        if (mb + kPre < MB) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) pv[mb + kPre][b] = pa[(32 * (mb + kPre) + 8 * b) / 4];
+        }
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const float4 v4 = pa[(32 * mb + 8 * b) / 4];  // primal: a / 2pi; tangent: dA / 2pi
+          const float4 v4 = pv[mb][b];
           const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
           float ab4[4];
 #pragma unroll
