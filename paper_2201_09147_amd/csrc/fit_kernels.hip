@@ -1,13 +1,14 @@
 // fit_kernels.hip -- fitting a SIREN through its analytic gradient (double
 // backward) on gfx950, in float32.
 //
-// One fused kernel per batch of points, tile by tile (8 points x the four
+// Two launches per batch of points over the same tiles (8 points x the four
 // columns [h | G_x G_y G_z] per wave, the tangent mode of the evaluator):
 //   forward   layer by layer with the shared-forward tangent (Alg. 2 in the
 //             G_i form), writing each layer's pre-activations (revolutions)
-//             and inputs to a workspace laid out [neuron][column];
-//   adjoints  of the loss terms, or the caller's upstream adjoints;
-//   reverse   through primal and tangent:
+//             and inputs to a workspace laid out [column][neuron];
+//   adjoints  of the loss terms, or the caller's upstream adjoints (end of
+//             the forward launch, one value per column);
+//   reverse   (second launch) through primal and tangent:
 //               abar_i  = cos(a_i) hbar_{i+1} - sin(a_i) sum_j Tbar_{i+1,j} dA_{i,j}
 //               dAbar_i = cos(a_i) Tbar_{i+1}
 //               [hbar_i | Tbar_i] = W_i^T [abar_i | dAbar_i]   (32x32x2 MFMAs)
