@@ -977,7 +977,7 @@ FitLayout fit_layout(const nnm_net_shape& sh, int64_t n, int grid) {
   return L;
 }
 
-// Packs `params` and runs the fused forward/adjoint/reverse kernel plus the
+// Packs `params` and runs the forward/adjoint and reverse launches plus the
 // gradient products.  mode 0: loss (batch), mode 1: upstream adjoints.
 int fit_backward_impl(const nnm_net_shape& sh, const float* params, int device, int grid, char* ws,
                       const FitLayout& FL, int mode, int64_t n, int64_t n_surf, const float* x0, const float* x1,
