@@ -234,7 +234,9 @@ int fit_create(const nnm_net_shape* shape, const float* params, int device, int6
 void fit_free(nnm_fit* fit);
 
 /* One step: loss, gradient through the double backward, Adam update.  loss4:
-   device [4] out (the four mean terms), or NULL.  Asynchronous on `stream`. */
+   device [4] out (the four mean terms), or NULL.  Asynchronous on `stream`.
+   Every sum over points runs over a fixed partition in a fixed order, so the
+   same state and batch give bitwise the same step on the same device. */
 int fit_step(nnm_fit* fit, const nnm_fit_batch* batch, const nnm_adam* opt, float* loss4, void* stream);
 
 /* Loss terms and gradient only (no update): dparams device [P] out. */
