@@ -123,6 +123,12 @@ def test_adam_step_and_determinism():
     fit.loss_grad(*args, loss, dp1)
     fit.loss_grad(*args, loss, dp2)
     assert torch.equal(dp1, dp2), "gradient is not bitwise reproducible"
+    # the reduction partitions follow the batch, not the workspace size
+    other = _fit(net, 1 << 16)
+    dp3 = torch.empty_like(dp1)
+    other.loss_grad(*args, loss, dp3)
+    other.close()
+    assert torch.equal(dp1, dp3), "gradient depends on the fit's max_points"
     lr = 1e-4
     fit.step_adam(*args, lr=lr)
     p_gpu = fit.params()
