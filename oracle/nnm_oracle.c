@@ -245,6 +245,8 @@ typedef struct {
    - the last traced level uses delta = 0 (the ternary of Algorithm 1);
    - level switch when d <= eps; a miss when tau > far or when a level has used
      max_steps evaluations; a non-finite d is a miss flagged NONFINITE;
+   - steps[j] counts the evaluations made at level j, on every exit (the one
+     that ends the ray included), and stays 0 for levels never reached;
    - d < 0 (a start inside the band, which Algorithm 1 excludes) is flagged;
    - depth is the ray parameter tau of the point after the last step.
    Fixed-iteration mode (the paper's experiments fix the iteration counts): level
@@ -272,6 +274,7 @@ static int trace_one(const orc_level* lv, const orc_base_desc* B, const orc_trac
       }
       if (!isfinite(d)) {
         st |= ORC_ST_NONFINITE;
+        if (steps) steps[j] = (uint8_t)k;
         goto miss;
       }
       if (d < 0.0) st |= ORC_ST_NEG_STEP;

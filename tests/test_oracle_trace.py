@@ -286,3 +286,105 @@ def test_fixed_iterations_sphere_recursion():
         # hits carry the sphere's radial normal
         p = o64[hit] + tau[hit, None] * v64[hit]
         np.testing.assert_allclose(r["normal"][hit], p / np.linalg.norm(p, axis=1, keepdims=True), atol=1e-12)
+
+
+def _sphere_eps_counts(o, v, deltas, s, cap=4000):
+    """Evaluations per level that eps-terminated tracing of the analytic sphere
+    needs without a budget: at level j the recursion
+    tau <- tau + s (|o + tau v| - 0.6 - delta_j) runs until its value d <= eps.
+    Also returns the smallest margin |d - eps| met at a level exit (to skip rays
+    whose count could depend on rounding)."""
+    o64, v64 = o.astype(np.float64), v.astype(np.float64)
+    n = o.shape[0]
+    m = len(deltas)
+    tau = np.zeros(n)
+    counts = np.zeros((n, m), np.int64)
+    margin = np.full(n, np.inf)
+    reach = np.ones(n, bool)
+    for j, delta in enumerate(deltas):
+        active = reach.copy()
+        k = np.zeros(n, np.int64)
+        for _ in range(cap):
+            if not active.any():
+                break
+            p = o64 + tau[:, None] * v64
+            d = np.sqrt(np.sum(p * p, axis=1)) - 0.6 - delta
+            k = np.where(active, k + 1, k)
+            tau = np.where(active, tau + s.step_scale * d, tau)
+            reach &= ~(active & (tau > s.far))
+            done = active & (d <= s.eps)
+            margin = np.where(active, np.minimum(margin, np.abs(d - s.eps)), margin)
+            active &= ~done & (tau <= s.far)
+        counts[:, j] = k
+    return counts, reach, margin
+
+
+def test_budget_pins_on_axis_closed_form():
+    """Algorithm 1's per-level budget on the analytic sphere, from a closed form.
+    A ray from (0,0,2.5) straight at the centre meets the level-j band at
+    distance 1.9 - (0.6 + delta_j) along the ray; each step removes the fraction
+    s = 0.9 of what is left, so the k-th evaluation sees d_1 (1 - s)^(k-1).
+    With deltas (0.05, 0.01, 0) and eps = 1e-4 the counts are 6, 4, 4:
+    1.85e-5 <= eps < 1.85e-4; then d_1 = 0.04 + 1.85e-6 gives 4.0e-5 at k = 4;
+    then d_1 = 0.01 + 4.0e-6 gives 1.0004e-4 > eps at k = 3 and 1.0e-5 at k = 4.
+    A budget of k - 1 must miss with that level's count equal to the budget;
+    a budget of exactly k must hit (the budget counts evaluations)."""
+    s = ni.make_scene("stack3_512sq").with_amplitudes([0.0, 0.0, 0.0])
+    o = np.array([[0.0, 0.0, 2.5]], np.float32)
+    v = np.array([[0.0, 0.0, -1.0]], np.float32)
+    need = [6, 4, 4]
+    for budget in range(1, 9):
+        s.max_steps = budget
+        r = T.trace(s, o, v)
+        first_short = next((j for j, kj in enumerate(need) if kj > budget), None)
+        if first_short is None:
+            assert r["hit"][0] == 1 and r["status"][0] == T.ST_HIT, budget
+            assert list(r["steps"][0]) == need
+            assert abs(r["depth"][0] - 1.9) <= s.eps
+        else:
+            assert r["hit"][0] == 0 and r["status"][0] == T.ST_BUDGET, budget
+            want = [need[j] if j < first_short else (budget if j == first_short else 0) for j in range(3)]
+            assert list(r["steps"][0]) == want, (budget, list(r["steps"][0]))
+            assert np.isinf(r["depth"][0]) and np.all(r["normal"][0] == 0.0)
+
+
+def test_budget_pins_recursion_many_rays():
+    """The per-level budget on many rays of the analytic sphere: for every
+    budget B, a ray hits iff each level's count k_j <= B, a miss at the first
+    level with k_j > B is flagged BUDGET with steps = (k_0, ..., k_{j-1}, B, 0...),
+    and a hit reports every k_j (so B = k_j - 1, k_j, k_j + 1 all occur)."""
+    s = ni.make_scene("stack3_512sq").with_size(40, 40).with_amplitudes([0.0, 0.0, 0.0])
+    o, v, _ = s.rays()
+    deltas = [s.levels[0].delta, s.levels[1].delta, 0.0]
+    need, reach, margin = _sphere_eps_counts(o, v, deltas, s)
+    keep = reach & (margin > 1e-9) & (need.max(axis=1) <= 40)
+    o, v, need = o[keep], v[keep], need[keep]
+    kmax = need.max(axis=1)
+    assert keep.sum() > 300 and len(np.unique(kmax)) >= 3
+    for budget in range(int(kmax.min()) - 1, int(kmax.max()) + 2):
+        s.max_steps = budget
+        r = T.trace(s, o, v)
+        hit = kmax <= budget
+        assert np.array_equal(r["hit"] == 1, hit), budget
+        assert np.all(r["status"][hit] == T.ST_HIT)
+        assert np.array_equal(r["steps"][hit], need[hit].astype(np.uint8))
+        assert np.all(r["status"][~hit] == T.ST_BUDGET)
+        for i in np.nonzero(~hit)[0]:
+            j = int(np.argmax(need[i] > budget))
+            want = np.concatenate([need[i, :j], [budget], np.zeros(2 - j, np.int64)])
+            assert np.array_equal(r["steps"][i], want.astype(np.uint8)), (budget, i)
+
+
+def test_nonfinite_ray_status_and_steps():
+    """A ray whose scene value is not finite is a miss flagged NONFINITE, and the
+    evaluation that produced it counts on its level (a NaN origin fails at the
+    first evaluation of level 0; the finite rays beside it are untouched)."""
+    s = ni.make_scene("stack3_512sq")
+    o = np.array([[np.nan, 0.0, 2.5], [0.0, 0.0, 2.5], [0.0, np.inf, 2.5]], np.float32)
+    v = np.array([[0.0, 0.0, -1.0], [0.0, 0.0, -1.0], [0.0, 0.0, -1.0]], np.float32)
+    r = T.trace(s, o, v)
+    for i in (0, 2):
+        assert r["hit"][i] == 0 and r["status"][i] == T.ST_NONFINITE
+        assert list(r["steps"][i]) == [1, 0, 0]
+        assert np.isinf(r["depth"][i]) and np.all(r["normal"][i] == 0.0)
+    assert r["hit"][1] == 1
