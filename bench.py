@@ -377,12 +377,7 @@ def run_nesting(workload, precision, n=100_000_000):
         pairs.append({"levels": [j - 1, j], "sup_abs_diff": sup, "points": n, "ms": round(ms, 2),
                       "points_per_s": round(n / (ms * 1e-3), 1)})
         log(f"[nesting] sup |f{j} - f{j - 1}| over 1e8 points = {sup:.6f} ({ms:.1f} ms)")
-    eps = [p_["sup_abs_diff"] + 1e-4 for p_ in pairs]
-    deltas = [0.0] * stack.m
-    if stack.m > 1:
-        deltas[-1] = eps[-1]
-        for i in range(stack.m - 1, 0, -1):
-            deltas[i - 1] = deltas[i] + eps[i - 1]
+    deltas = nnm.nnm_nesting_thresholds(1, [0.0] + [p_["sup_abs_diff"] for p_ in pairs], 1e-4)
     stack.close()
     return {"workload": workload, "precision": precision, "pairs": pairs,
             "prop1_deltas": [round(d, 6) for d in deltas],
@@ -495,9 +490,9 @@ def _clip_to_box(o_np, v_np):
 
 
 def run_capacity(steps=2000):
-    """Capacity-sequence training (Sec. 4.2): the three shapes of the nested
+    """Capacity-sequence training (Sec. 3.3): the three shapes of the nested
     stack, (32,1), (64,1) and (256,2), fitted to the torus on the same batches;
-    nesting thresholds from the sampled sup |f_j - f_(j-1)| by Proposition 1;
+    nesting thresholds from the sampled sup |torus - f_j| by Proposition 2;
     then multiscale sphere tracing of the trained stack at 1080p against single-
     level tracing of the finest net and against the exact torus."""
     import concurrent.futures as cf
@@ -539,17 +534,17 @@ def run_capacity(steps=2000):
         lv = [ni.SceneLevel(n_, 1.0, d) for n_, d in zip(levels, deltas)]
         return ni.Scene("capacity_torus", lv, 1920, 1080, r0=0.0, base_sphere=False)
 
-    # thresholds by Proposition 1 on the training domain
+    # thresholds on the training domain [-1, 1]^3: Proposition 2 from the sampled
+    # sup |torus - f_j| (the nets approximate one known SDF), and Proposition 1
+    # from the sampled sup |f_j - f_(j-1)| beside it; the render uses Proposition 2
     probe = nnm.load_siren_stack(make(fitted, [1.0, 0.5, 0.0]), "fp32", 0, lipschitz_max=0.0)
-    sups = [nnm.nnm_sup_abs_diff(probe, j, j - 1, 1 << 26, 77 + j, -1.0, 1.0) for j in (1, 2)]
+    d_p2, sups_p2 = nnm.capacity_thresholds(probe, "torus", ni.torus.R_MAJOR, ni.torus.R_MINOR, 1 << 26, 77, -1.0, 1.0,
+                                            margin=1e-3)
+    d_p1, sups_p1 = nnm.nesting_thresholds(probe, 1 << 26, 77, -1.0, 1.0, margin=1e-3)
     probe.close()
-    # Prop. 1 (zero-based): eps_j > sup |f_j - f_(j-1)|; delta_2 = eps_2,
-    # delta_1 = delta_2 + eps_2, delta_0 = delta_1 + eps_1 (delta_2 is the fine
-    # net's band, unused: the last level is traced to its zero set)
-    margin = 1e-3
-    eps = [sups[0] + margin, sups[1] + margin]
-    deltas = [2 * eps[1] + eps[0], 2 * eps[1]]
-    log(f"[capacity] sup |f1 - f0| = {sups[0]:.5f}, sup |f2 - f1| = {sups[1]:.5f}; deltas {deltas}")
+    deltas = d_p2[:2]
+    log(f"[capacity] sup |torus - f_j| = {[round(x, 5) for x in sups_p2]}: Prop. 2 deltas {deltas}; "
+        f"sup |f_j - f_(j-1)| = {[round(x, 5) for x in sups_p1]}: Prop. 1 deltas {d_p1[:2]}")
     o_np, v_np, _ = make(fitted, deltas + [0.0]).rays()
     t_in, t_out = _clip_to_box(o_np, v_np)
     inbox = np.flatnonzero(t_out > t_in)
@@ -599,7 +594,8 @@ def run_capacity(steps=2000):
         r.pop("_hit")
     return {"steps": steps, "wall_s": round(wall, 2), "nets": ["(32,1)", "(64,1)", "(256,2)"],
             "adam_lr": [sh[3] for sh in shapes],
-            "final_loss4": final_loss, "sup_abs_diff": sups, "deltas_prop1": deltas, "renders_1080p": out_rows}
+            "final_loss4": final_loss, "sup_abs_err_vs_torus": sups_p2, "deltas_prop2": d_p2,
+            "sup_abs_diff": sups_p1, "deltas_prop1": d_p1, "renders_1080p": out_rows}
 
 
 def roofline(form):

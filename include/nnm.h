@@ -100,6 +100,14 @@ typedef struct nnm_stack nnm_stack; /* opaque; immutable after loading */
 #define NNM_MAX_LEVELS 8
 typedef struct nnm_profiler nnm_profiler; /* see "profiling" below */
 
+/* Kernel family of trace_rays.  Both compute the same Algorithm 1 and normals;
+   they differ in the order of the float32 sums inside a layer.
+   AUTO: the pipelined weight-stationary kernels on the levels that have them
+   (width 256, two hidden layers, bf16/fp16), the streaming tile elsewhere.
+   STREAMING: the streaming tile on every level. */
+#define NNM_KERNELS_AUTO 0
+#define NNM_KERNELS_STREAMING 1
+
 typedef struct {
   float step_scale;      /* s, in (0, 1] */
   float eps;             /* eps > 0 */
@@ -109,7 +117,7 @@ typedef struct {
   int32_t normal_level;  /* level whose unit gradient is returned as the normal;
                             > final_level is neural normal mapping (Sec. 5) */
   int32_t mode;          /* 0: eps-terminated; 1: fixed iterations per level */
-  int32_t reserved;
+  int32_t kernels;       /* NNM_KERNELS_AUTO or NNM_KERNELS_STREAMING */
   nnm_profiler* profiler; /* NULL, or a profiler that times every kernel of the call */
   int32_t iterations[NNM_MAX_LEVELS]; /* mode 1: steps of each traced level */
 } nnm_trace_params;
@@ -263,10 +271,9 @@ int fit_set_step(nnm_fit* fit, int64_t step);
 
 /* Sampled infinity norm of f_a - f_b, the scene functions of two levels of a
    stack, over the box [lo, hi]^3 (and t in [0, 1) when a level is 4-D or the
-   base moves): Sec. 4.2 approximates |f|_inf by a maximum over sampled
-   points, and Propositions 1-2 turn such bounds into nesting thresholds
-   (Prop. 1: delta_m = eps_m, delta_{i-1} = delta_i + eps_i with
-   eps_i > |f_i - f_{i-1}|_inf).  n points are drawn by splitmix64 from seed:
+   base moves): Sec. 3.3 approximates |f|_inf by a maximum over sampled
+   points, and Proposition 1 turns such bounds into nesting thresholds
+   (nnm_nesting_thresholds).  n points are drawn by splitmix64 from seed:
    stream position k = 4 i + c for coordinate c of point i, u = (z >> 40) / 2^24,
    x_c = float(lo + (hi - lo) u) evaluated in double, t = float(u) of c = 3.
    out_max: one device float, overwritten (a NaN difference gives +inf).
@@ -275,6 +282,53 @@ int fit_set_step(nnm_fit* fit, int64_t step);
    NNM_E_DEVICE. */
 int nnm_sup_abs_diff(const nnm_stack* s, int level_a, int level_b, int64_t n, uint64_t seed, float lo, float hi,
                      float* out_max, void* stream);
+
+/* A known signed distance function f, the target that the networks of
+   Proposition 2 approximate ("MLPs for a single surface", Sec. 3.3), evaluated
+   in float32:
+     NNM_REF_SPHERE  |x| - a
+     NNM_REF_TORUS   sqrt((sqrt(x^2 + y^2) - a)^2 + z^2) - b  (axis z, major
+                     radius a, minor radius b) */
+#define NNM_REF_SPHERE 1
+#define NNM_REF_TORUS 2
+typedef struct {
+  int32_t kind; /* NNM_REF_SPHERE or NNM_REF_TORUS */
+  float a;      /* radius (sphere) or major radius (torus), > 0 */
+  float b;      /* minor radius (torus), > 0; unused for the sphere */
+  int32_t reserved;
+} nnm_ref_sdf;
+
+/* Sampled infinity norm of f - f_level: the scene function of one level
+   against a known SDF, over the same splitmix64 points as nnm_sup_abs_diff
+   (same seed, same n, same box give the same points).  The bound
+   |f - f_theta_i|_inf < eps_i that Proposition 2 turns into thresholds.
+   out_max: one device float, overwritten (a NaN difference gives +inf).
+   Asynchronous on `stream`; stream-ordered scratch of about 24 MB.
+   Errors: NNM_E_INVAL (null, bad level, n < 1, empty box, unknown shape or
+   non-positive radius), NNM_E_NOMEM, NNM_E_DEVICE. */
+int nnm_sup_abs_err(const nnm_stack* s, int level, const nnm_ref_sdf* ref, int64_t n, uint64_t seed, float lo,
+                    float hi, float* out_max, void* stream);
+
+/* Nesting thresholds from bounds on infinity norms (Sec. 3.3, Propositions 1
+   and 2).  Host only, float64, no device use.  Each bound becomes
+   eps_i = sup[i] + margin: the propositions need strict bounds
+   (eps_i > |.|_inf), and a sampled maximum approaches the supremum from below,
+   so margin (>= 0) is the caller's allowance for that.  0-based levels:
+     NNM_NEST_PROP1  consecutive members, sup[i] >= |f_i - f_{i-1}|_inf for
+                     i = 1 .. m-1 (sup[0] is not read):
+                       delta[m-1] = eps_{m-1},
+                       delta[i-1] = delta[i] + eps_i          (i = m-1 .. 1)
+     NNM_NEST_PROP2  members approximating one SDF f, sup[i] >= |f - f_i|_inf
+                     for i = 0 .. m-1:
+                       delta[m-1] = eps_{m-1} + eps_{m-2},
+                       delta[i-1] = delta[i] + eps_i + eps_{i-1}  (i = m-1 .. 1)
+   Writes delta[0 .. m-1]; trace_rays reads delta[0 .. m-2] (the level
+   descriptors' delta) and traces the last level to its zero set.
+   Errors: NNM_E_INVAL (null, m outside 2 .. NNM_MAX_LEVELS, unknown
+   proposition, a negative or non-finite bound or margin). */
+#define NNM_NEST_PROP1 1
+#define NNM_NEST_PROP2 2
+int nnm_nesting_thresholds(int proposition, int32_t m, const double* sup, double margin, double* delta);
 
 /* ------------------------------------------- neural normal mapping on meshes */
 

@@ -183,10 +183,12 @@ static double net_value_grad(const orc_net* net, const double* in, double grad[3
   return out;
 }
 
+/* c(t) = rho (cos 2 pi t, sin 2 pi t, 0); rho = 0 is the static centre c = 0,
+   whatever t holds. */
 static void center_at(double rho, double t, double c[3]) {
   const double two_pi = 6.283185307179586476925286766559;
-  c[0] = rho * cos(two_pi * t);
-  c[1] = rho * sin(two_pi * t);
+  c[0] = rho == 0.0 ? 0.0 : rho * cos(two_pi * t);
+  c[1] = rho == 0.0 ? 0.0 : rho * sin(two_pi * t);
   c[2] = 0.0;
 }
 

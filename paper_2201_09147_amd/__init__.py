@@ -8,7 +8,8 @@ streams (default: the current stream).
 
 Entry points (same names as the C ABI in include/nnm.h):
   load_siren_stack, free_siren_stack, trace_rays, analytic_normal,
-  nnm_net_eval, nnm_sup_abs_diff, neural_normal_map, nnm_grid_values,
+  nnm_net_eval, nnm_sup_abs_diff, nnm_sup_abs_err, nnm_nesting_thresholds,
+  neural_normal_map, nnm_grid_values,
   nnm_mesh_extract, nnm_validate_stack, nnm_read_net_file, nnm_sync
 plus ``render`` (allocates outputs and calls trace_rays), ``extract_mesh`` and
 ``mesh_neural_normal_map`` (coarse mesh + fine normals), the fitting entry
@@ -36,7 +37,11 @@ from ._binding import (  # noqa: F401
     analytic_normal,
     nnm_net_eval,
     nnm_sup_abs_diff,
+    nnm_sup_abs_err,
+    nnm_nesting_thresholds,
     nesting_thresholds,
+    capacity_thresholds,
+    KERNELS,
     neural_normal_map,
     nnm_grid_values,
     nnm_mesh_extract,

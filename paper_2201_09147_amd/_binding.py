@@ -9,8 +9,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# NNM_LIBRARY selects another build of the same library (e.g. a tuning variant).
-_LIB_PATH = os.environ.get("NNM_LIBRARY") or os.path.join(_HERE, "libnnm.so")
+_DEFAULT_LIB = os.path.join(_HERE, "libnnm.so")
+_LIB_PATH = _DEFAULT_LIB
 
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 ST_HIT, ST_FAR, ST_BUDGET, ST_NEG_STEP, ST_NONFINITE = 1, 2, 4, 8, 16
@@ -37,7 +37,15 @@ class _StackDesc(ctypes.Structure):
 class _TraceParams(ctypes.Structure):
     _fields_ = [("step_scale", c_float), ("eps", c_float), ("far", c_float), ("max_steps", c_int32),
                 ("final_level", c_int32), ("normal_level", c_int32), ("mode", c_int32),
-                ("reserved", c_int32), ("profiler", c_void_p), ("iterations", c_int32 * 8)]
+                ("kernels", c_int32), ("profiler", c_void_p), ("iterations", c_int32 * 8)]
+
+
+class _RefSdf(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("a", c_float), ("b", c_float), ("reserved", c_int32)]
+
+
+KERNELS = {"auto": 0, "streaming": 1}
+REF_SHAPES = {"sphere": 1, "torus": 2}
 
 
 _PROF_MAX = 32
@@ -56,9 +64,17 @@ def library_path() -> str:
     return _LIB_PATH
 
 
-def load_library():
-    """Load libnnm.so (raises NnmError when it has not been built)."""
-    global _lib
+def load_library(path: Optional[str] = None):
+    """Load libnnm.so (raises NnmError when it has not been built).
+
+    ``path`` names another build of the same library (a tuning variant); it
+    must be given before the first call into the library, and a later call
+    naming a different file raises."""
+    global _lib, _LIB_PATH
+    if path is not None and os.path.abspath(path) != os.path.abspath(_LIB_PATH):
+        if _lib is not None:
+            raise NnmError(-1, f"{_LIB_PATH} is already loaded; cannot switch to {path}")
+        _LIB_PATH = os.path.abspath(path)
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
@@ -76,6 +92,8 @@ def load_library():
         "analytic_normal": ([P, c_int, c_int64, P, P, P, P, P], c_int),
         "nnm_net_eval": ([P, c_int, c_int64, P, P, P, P, P], c_int),
         "nnm_sup_abs_diff": ([P, c_int, c_int, c_int64, ctypes.c_uint64, ctypes.c_float, ctypes.c_float, P, P], c_int),
+        "nnm_sup_abs_err": ([P, c_int, P, c_int64, ctypes.c_uint64, ctypes.c_float, ctypes.c_float, P, P], c_int),
+        "nnm_nesting_thresholds": ([c_int, c_int32, P, c_double, P], c_int),
         "neural_normal_map": ([P, c_int, c_int64, P, P, P, P], c_int),
         "nnm_grid_values": ([P, c_int, c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float, P, P], c_int),
         "nnm_mesh_extract": ([P, c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float, c_int64, c_int64, P, P, P,
@@ -286,6 +304,7 @@ class TraceParams:
     mode: int = 0
     profiler: Optional[Profiler] = None
     iterations: Optional[Sequence[int]] = None  # fixed-iteration mode (mode 1): steps per traced level
+    kernels: str = "auto"  # "auto" (weight-stationary where available) or "streaming"
 
     def c(self, m: int) -> _TraceParams:
         fl = m - 1 if self.final_level < 0 else self.final_level
@@ -297,7 +316,8 @@ class TraceParams:
             mode = 1
             for j, k in enumerate(self.iterations):
                 its[j] = int(k)
-        return _TraceParams(self.step_scale, self.eps, self.far, self.max_steps, fl, nl, mode, 0, prof, its)
+        return _TraceParams(self.step_scale, self.eps, self.far, self.max_steps, fl, nl, mode,
+                            KERNELS[self.kernels], prof, its)
 
 
 def _dev_ptr(t, dtype, shape, name, device, allow_none=True):
@@ -382,19 +402,51 @@ def nnm_sup_abs_diff(stack: Stack, level_a: int, level_b: int, n: int, seed: int
     return float(out.item())
 
 
+def nnm_sup_abs_err(stack: Stack, level: int, shape: str, a: float, b: float = 0.0, n: int = 1 << 24,
+                    seed: int = 0, lo: float = -1.0, hi: float = 1.0, out=None, stream=None) -> float:
+    """Sampled sup |f - f_level| against a reference SDF ("sphere": radius a;
+    "torus": major radius a, minor radius b, axis z) over [lo, hi]^3
+    (nnm_sup_abs_err); returns it as a float."""
+    import torch
+    dev = torch.device("cuda", stack.device)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float32, device=dev)
+    if shape not in REF_SHAPES:
+        raise NnmError(-1, f"reference shape {shape!r} (sphere or torus)")
+    ref = _RefSdf(REF_SHAPES[shape], float(a), float(b), 0)
+    _check(load_library().nnm_sup_abs_err(stack.handle, int(level), ctypes.byref(ref), ctypes.c_int64(int(n)),
+                                          ctypes.c_uint64(int(seed)), ctypes.c_float(lo), ctypes.c_float(hi),
+                                          _dev_ptr(out, torch.float32, (1,), "out", stack.device, False),
+                                          _stream_ptr(stream, stack.device)))
+    return float(out.item())
+
+
+def nnm_nesting_thresholds(proposition: int, sup: Sequence[float], margin: float = 0.0) -> List[float]:
+    """Thresholds delta[0 .. m-1] from sampled bounds by Proposition 1 or 2
+    (nnm_nesting_thresholds; for proposition 1, sup[0] is not read)."""
+    m = len(sup)
+    arr = (c_double * max(m, 1))(*[float(x) for x in sup])
+    out = (c_double * max(m, 1))()
+    _check(load_library().nnm_nesting_thresholds(int(proposition), m, arr, float(margin), out))
+    return [out[i] for i in range(m)]
+
+
 def nesting_thresholds(stack: Stack, n: int = 1 << 24, seed: int = 0, lo: float = -1.5, hi: float = 1.5,
                        margin: float = 1e-4):
-    """Thresholds by Proposition 1 from sampled bounds eps_i = sup |f_i - f_{i-1}| + margin
-    (i = 1 .. m-1, zero-based): delta_{m-1} = eps_{m-1}, delta_{i-1} = delta_i + eps_i.
-    Returns (deltas[m], eps[m-1])."""
-    m = stack.m
-    eps = [nnm_sup_abs_diff(stack, i, i - 1, n, seed + i, lo, hi) + margin for i in range(1, m)]
-    deltas = [0.0] * m
-    if m > 1:
-        deltas[m - 1] = eps[m - 2]
-        for i in range(m - 1, 0, -1):
-            deltas[i - 1] = deltas[i] + eps[i - 1]
-    return deltas, eps
+    """Proposition 1 thresholds from sampled bounds sup |f_i - f_{i-1}| (i = 1 .. m-1):
+    nnm_sup_abs_diff for each pair, then nnm_nesting_thresholds.
+    Returns (deltas[m], sups[m-1])."""
+    sups = [nnm_sup_abs_diff(stack, i, i - 1, n, seed + i, lo, hi) for i in range(1, stack.m)]
+    return nnm_nesting_thresholds(1, [0.0] + sups, margin), sups
+
+
+def capacity_thresholds(stack: Stack, shape: str, a: float, b: float = 0.0, n: int = 1 << 24, seed: int = 0,
+                        lo: float = -1.0, hi: float = 1.0, margin: float = 1e-4):
+    """Proposition 2 thresholds for levels that approximate one known SDF:
+    nnm_sup_abs_err for each level, then nnm_nesting_thresholds.
+    Returns (deltas[m], sups[m])."""
+    sups = [nnm_sup_abs_err(stack, i, shape, a, b, n, seed, lo, hi) for i in range(stack.m)]
+    return nnm_nesting_thresholds(2, sups, margin), sups
 
 
 def neural_normal_map(stack: Stack, level: int, x, t=None, normal=None, stream=None):

@@ -1,6 +1,7 @@
-// nesting_kernels.hip -- sampled sup |f_a - f_b| over a box, the quantity the
-// paper's Propositions 1-2 turn into nesting thresholds (Sec. 4.2: the infinity
-// norm on the training domain, approximated by a maximum over sampled points).
+// nesting_kernels.hip -- sampled sup |f_a - f_b| over a box (two levels, or a
+// level and a reference shape's SDF), the quantity the paper's Propositions
+// 1-2 turn into nesting thresholds (Sec. 3.3: the infinity norm on the
+// training domain, approximated by a maximum over sampled points).
 //
 // Points come from a counter-based generator so that any other implementation
 // can reproduce them exactly: splitmix64 (Steele, Lea and Flood, 2014, with
@@ -47,6 +48,29 @@ __global__ void k_absdiff_max(const float* fa, const float* fb, int count, unsig
     __syncthreads();
   }
   if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
+}
+
+// Signed distance of a reference shape at points x[count][3], in float32:
+// kind 1 sphere |x| - a; kind 2 torus about the z axis with major radius a and
+// minor radius b, sqrt((sqrt(x^2 + y^2) - a)^2 + z^2) - b.
+__global__ void k_ref_sdf(const float* x, int count, int kind, float a, float b, float* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float px = x[3 * i], py = x[3 * i + 1], pz = x[3 * i + 2];
+  float d;
+  if (kind == 1) {
+    d = sqrtf(fmaf(px, px, fmaf(py, py, pz * pz))) - a;
+  } else {
+    const float q = sqrtf(fmaf(px, px, py * py)) - a;
+    d = sqrtf(fmaf(q, q, pz * pz)) - b;
+  }
+  out[i] = d;
+}
+
+hipError_t launch_ref_sdf(const float* x, int count, int kind, float a, float b, float* out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ref_sdf, dim3((count + 255) / 256), dim3(256), 0, s, x, count, kind, a, b, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_box_points(uint64_t seed, long long base, int count, float lo, float hi, float* x, float* t,

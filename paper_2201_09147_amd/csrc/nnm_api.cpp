@@ -218,7 +218,6 @@ struct nnm_stack {
   int device = 0;
   int precision = 0;
   int m = 0;
-  int use_ws = 1;  // weight-stationary kernels where a level has them (NNM_NO_WS=1 disables)
   DevBase base{};
   struct Level {
     int d_in, width, n_sine, follow_center;
@@ -479,10 +478,6 @@ int load_siren_stack(const nnm_stack_desc* d, int precision, int device, nnm_sta
   s->device = device;
   s->precision = precision;
   s->m = d->n_levels;
-  {
-    const char* no_ws = std::getenv("NNM_NO_WS");
-    s->use_ws = (no_ws && no_ws[0] == '1') ? 0 : 1;
-  }
   s->base.sphere = d->base_sphere ? 1 : 0;
   s->base.r0 = d->r0;
   s->base.rho = d->rho;
@@ -496,6 +491,13 @@ int load_siren_stack(const nnm_stack_desc* d, int precision, int device, nnm_sta
   }
   *out = s;
   return NNM_OK;
+}
+
+// A level reads the time when its network takes (x, t), or when its input or
+// the base term follows the moving centre c(t).
+static bool level_reads_time(const nnm_stack* s, int j) {
+  const auto& L = s->levels[j];
+  return L.d_in == 4 || (s->base.rho != 0.f && (s->base.sphere || L.follow_center));
 }
 
 int nnm_stack_levels(const nnm_stack* s) { return s ? s->m : -1; }
@@ -517,12 +519,20 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
   if (!(p->far > 0.f) || !std::isfinite(p->far)) return fail(NNM_E_INVAL, "far %g", p->far);
   if (p->max_steps < 1 || p->max_steps > 255) return fail(NNM_E_INVAL, "max_steps %d not in 1..255", p->max_steps);
   if (p->mode != 0 && p->mode != 1) return fail(NNM_E_INVAL, "trace mode %d", p->mode);
+  if (p->kernels != NNM_KERNELS_AUTO && p->kernels != NNM_KERNELS_STREAMING)
+    return fail(NNM_E_INVAL, "kernel family %d", p->kernels);
   if (p->mode == 1)
     for (int j = 0; j <= p->final_level; ++j)
       if (p->iterations[j] < 1 || p->iterations[j] > 255)
         return fail(NNM_E_INVAL, "iterations[%d] = %d not in 1..255", j, p->iterations[j]);
   if (n == 0) return NNM_OK;
   if (!o || !v || !depth || !hit) return fail(NNM_E_INVAL, "null ray or output array");
+  if (!t) {
+    for (int j = 0; j <= p->final_level; ++j)
+      if (level_reads_time(s, j)) return fail(NNM_E_INVAL, "null t, but level %d depends on the time", j);
+    if (normal && level_reads_time(s, p->normal_level))
+      return fail(NNM_E_INVAL, "null t, but normal level %d depends on the time", p->normal_level);
+  }
   DeviceGuard guard(s->device);
   if (!guard.ok) return fail(NNM_E_DEVICE, "hipSetDevice(%d) failed", s->device);
   hipStream_t st = (hipStream_t)stream;
@@ -576,7 +586,7 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
     a.far = p->far;
     a.fixed_iters = p->mode == 1 ? p->iterations[j] : 0;
     a.delta = is_final ? 0.f : lv.delta;
-    const bool ws_kernel = lv.dev.ws_ah && s->use_ws;
+    const bool ws_kernel = lv.dev.ws_ah && p->kernels == NNM_KERNELS_AUTO;
     ProfScope prof(p->profiler, 0, j, lv.width, ws_kernel ? 1 : 0, st);
     if (ws_kernel) {
       const long long want = ((long long)n + kWsRaysPerBlock - 1) / kWsRaysPerBlock;
@@ -601,7 +611,7 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
     a.queue = q[(L - 1) & 1];
     a.count = cnt + 2 * (L - 1) + 1;
     a.n = (int)n;
-    const bool ws_kernel = nl.dev.ws_ah && s->use_ws;
+    const bool ws_kernel = nl.dev.ws_ah && p->kernels == NNM_KERNELS_AUTO;
     ProfScope prof(p->profiler, 1, p->normal_level, nl.width, ws_kernel ? 1 : 0, st);
     if (ws_kernel) {
       const long long want = ((long long)n + kWsPointsPerBlock - 1) / kWsPointsPerBlock;
@@ -627,6 +637,7 @@ static int points_common(const nnm_stack* s, int level, int64_t n, const float* 
   if (n == 0) return NNM_OK;
   if (!x) return fail(NNM_E_INVAL, "null points");
   if (!value && !grad) return fail(NNM_E_INVAL, "no output requested");
+  if (!t && level_reads_time(s, level)) return fail(NNM_E_INVAL, "null t, but level %d depends on the time", level);
   DeviceGuard guard(s->device);
   if (!guard.ok) return fail(NNM_E_DEVICE, "hipSetDevice(%d) failed", s->device);
   const auto& lv = s->levels[level];
@@ -658,19 +669,15 @@ int nnm_net_eval(const nnm_stack* s, int level, int64_t n, const float* x, const
   return points_common(s, level, n, x, t, value, grad, stream, 1);
 }
 
-int nnm_sup_abs_diff(const nnm_stack* s, int level_a, int level_b, int64_t n, uint64_t seed, float lo, float hi,
-                     float* out_max, void* stream) {
-  g_err.clear();
-  if (!s || !out_max) return fail(NNM_E_INVAL, "null stack or output");
-  if (level_a < 0 || level_a >= s->m || level_b < 0 || level_b >= s->m)
-    return fail(NNM_E_INVAL, "levels %d, %d of %d", level_a, level_b, s->m);
-  if (n < 1) return fail(NNM_E_INVAL, "n = %lld < 1", (long long)n);
-  if (!(lo < hi) || !std::isfinite(lo) || !std::isfinite(hi)) return fail(NNM_E_INVAL, "box [%g, %g]", lo, hi);
+// Sampled maximum of |f_level_a - g| over n splitmix64 points of [lo, hi]^3,
+// where g is level_b's scene function or, when ref != null, a reference SDF.
+static int sup_abs_common(const nnm_stack* s, int level_a, int level_b, const nnm_ref_sdf* ref, int64_t n,
+                          uint64_t seed, float lo, float hi, float* out_max, void* stream) {
   DeviceGuard guard(s->device);
   if (!guard.ok) return fail(NNM_E_DEVICE, "hipSetDevice(%d) failed", s->device);
   hipStream_t st = (hipStream_t)stream;
   // time-conditioned nets or a moving base: the time is sampled too
-  const bool with_t = s->levels[level_a].d_in == 4 || s->levels[level_b].d_in == 4 || s->base.rho != 0.f;
+  const bool with_t = s->levels[level_a].d_in == 4 || (!ref && s->levels[level_b].d_in == 4) || s->base.rho != 0.f;
   const int chunk = (int)std::min<int64_t>(n, 1 << 22);
   const size_t off_x = 0, off_t = align256((size_t)chunk * 12), off_a = off_t + align256((size_t)chunk * 4),
                off_b = off_a + align256((size_t)chunk * 4);
@@ -692,11 +699,68 @@ int nnm_sup_abs_diff(const nnm_stack* s, int level_a, int level_b, int64_t n, ui
       break;
     }
     if ((rc = points_common(s, level_a, cnt, x, t, fa, nullptr, stream, 0)) != NNM_OK) break;
-    if ((rc = points_common(s, level_b, cnt, x, t, fb, nullptr, stream, 0)) != NNM_OK) break;
+    if (ref) {
+      if ((e = launch_ref_sdf(x, cnt, ref->kind, ref->a, ref->b, fb, st)) != hipSuccess) {
+        rc = hip_fail(e, "reference SDF");
+        break;
+      }
+    } else if ((rc = points_common(s, level_b, cnt, x, t, fb, nullptr, stream, 0)) != NNM_OK) {
+      break;
+    }
     if ((e = launch_absdiff_max(fa, fb, cnt, (unsigned int*)out_max, st)) != hipSuccess) rc = hip_fail(e, "max reduction");
   }
   if ((e = hipFreeAsync(ws, st)) != hipSuccess && rc == NNM_OK) rc = hip_fail(e, "hipFreeAsync");
   return rc;
+}
+
+int nnm_sup_abs_diff(const nnm_stack* s, int level_a, int level_b, int64_t n, uint64_t seed, float lo, float hi,
+                     float* out_max, void* stream) {
+  g_err.clear();
+  if (!s || !out_max) return fail(NNM_E_INVAL, "null stack or output");
+  if (level_a < 0 || level_a >= s->m || level_b < 0 || level_b >= s->m)
+    return fail(NNM_E_INVAL, "levels %d, %d of %d", level_a, level_b, s->m);
+  if (n < 1) return fail(NNM_E_INVAL, "n = %lld < 1", (long long)n);
+  if (!(lo < hi) || !std::isfinite(lo) || !std::isfinite(hi)) return fail(NNM_E_INVAL, "box [%g, %g]", lo, hi);
+  return sup_abs_common(s, level_a, level_b, nullptr, n, seed, lo, hi, out_max, stream);
+}
+
+int nnm_sup_abs_err(const nnm_stack* s, int level, const nnm_ref_sdf* ref, int64_t n, uint64_t seed, float lo,
+                    float hi, float* out_max, void* stream) {
+  g_err.clear();
+  if (!s || !ref || !out_max) return fail(NNM_E_INVAL, "null stack, shape or output");
+  if (level < 0 || level >= s->m) return fail(NNM_E_INVAL, "level %d of %d", level, s->m);
+  if (n < 1) return fail(NNM_E_INVAL, "n = %lld < 1", (long long)n);
+  if (!(lo < hi) || !std::isfinite(lo) || !std::isfinite(hi)) return fail(NNM_E_INVAL, "box [%g, %g]", lo, hi);
+  if (ref->kind != NNM_REF_SPHERE && ref->kind != NNM_REF_TORUS) return fail(NNM_E_INVAL, "reference shape %d", ref->kind);
+  if (!(ref->a > 0.f) || !std::isfinite(ref->a) || (ref->kind == NNM_REF_TORUS && (!(ref->b > 0.f) || !std::isfinite(ref->b))))
+    return fail(NNM_E_INVAL, "reference radii %g, %g", ref->a, ref->b);
+  return sup_abs_common(s, level, -1, ref, n, seed, lo, hi, out_max, stream);
+}
+
+int nnm_nesting_thresholds(int proposition, int32_t m, const double* sup, double margin, double* delta) {
+  g_err.clear();
+  if (!sup || !delta) return fail(NNM_E_INVAL, "null bounds or output");
+  if (m < 2 || m > NNM_MAX_LEVELS) return fail(NNM_E_INVAL, "m = %d outside 2..%d", m, NNM_MAX_LEVELS);
+  if (proposition != NNM_NEST_PROP1 && proposition != NNM_NEST_PROP2)
+    return fail(NNM_E_INVAL, "proposition %d (1 or 2)", proposition);
+  if (!(margin >= 0.0) || !std::isfinite(margin)) return fail(NNM_E_INVAL, "margin %g", margin);
+  const int first = proposition == NNM_NEST_PROP1 ? 1 : 0;
+  double eps[NNM_MAX_LEVELS] = {0.0};
+  for (int i = first; i < m; ++i) {
+    if (!(sup[i] >= 0.0) || !std::isfinite(sup[i])) return fail(NNM_E_INVAL, "bound %d = %g", i, sup[i]);
+    eps[i] = sup[i] + margin;
+  }
+  if (proposition == NNM_NEST_PROP1) {
+    // Proposition 1: |f_i - f_{i-1}| < eps_i gives delta_m = eps_m, delta_{i-1} = delta_i + eps_i.
+    delta[m - 1] = eps[m - 1];
+    for (int i = m - 1; i >= 1; --i) delta[i - 1] = delta[i] + eps[i];
+  } else {
+    // Proposition 2: |f - f_i| < eps_i gives delta_m = eps_m + eps_{m-1},
+    // delta_{i-1} = delta_i + eps_i + eps_{i-1}.
+    delta[m - 1] = eps[m - 1] + eps[m - 2];
+    for (int i = m - 1; i >= 1; --i) delta[i - 1] = delta[i] + eps[i] + eps[i - 1];
+  }
+  return NNM_OK;
 }
 
 int neural_normal_map(const nnm_stack* s, int level, int64_t n, const float* x, const float* t, float* normal,
@@ -708,6 +772,7 @@ int neural_normal_map(const nnm_stack* s, int level, int64_t n, const float* x, 
   if (n > (int64_t)INT_MAX - (1 << 24)) return fail(NNM_E_INVAL, "n = %lld too large", (long long)n);
   if (n == 0) return NNM_OK;
   if (!x || !normal) return fail(NNM_E_INVAL, "null points or normals");
+  if (!t && level_reads_time(s, level)) return fail(NNM_E_INVAL, "null t, but level %d depends on the time", level);
   DeviceGuard guard(s->device);
   if (!guard.ok) return fail(NNM_E_DEVICE, "hipSetDevice(%d) failed", s->device);
   const auto& lv = s->levels[level];
@@ -719,7 +784,7 @@ int neural_normal_map(const nnm_stack* s, int level, int64_t n, const float* x, 
   a.n = (int)n;
   a.x = x;
   hipError_t e;
-  if (lv.dev.ws_ah && s->use_ws) {
+  if (lv.dev.ws_ah) {
     const long long want = (n + kWsPointsPerBlock - 1) / kWsPointsPerBlock;
     const int grid = (int)std::max(1LL, std::min(want, (long long)lv.ws_resident[1]));
     e = launch_normal_ws(s->precision, a, grid, (hipStream_t)stream);

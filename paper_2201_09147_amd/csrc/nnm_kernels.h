@@ -176,6 +176,7 @@ hipError_t launch_masked_sum(const float* a, const float* m, long long n, int cs
 hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
 hipError_t launch_box_points(uint64_t seed, long long base, int count, float lo, float hi, float* x, float* t,
                              hipStream_t s);
+hipError_t launch_ref_sdf(const float* x, int count, int kind, float a, float b, float* out, hipStream_t s);
 hipError_t launch_absdiff_max(const float* fa, const float* fb, int count, unsigned int* out, hipStream_t s);
 hipError_t launch_trace_level(int width, int prec, const TraceLevelArgs& a, int grid, hipStream_t s);
 hipError_t launch_normal(int width, int prec, const NormalArgs& a, int grid, hipStream_t s);

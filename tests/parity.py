@@ -11,14 +11,16 @@ LOWP_MEAN_ANGLE_DEG = 0.5
 NET_REL_L2 = {"fp32": 1e-5, "bf16": 3e-2, "fp16": 5e-3}
 
 
-def gpu_trace(scene, o, v, t=None, precision="fp32", final_level=-1, normal_level=-1, stack=None):
+def gpu_trace(scene, o, v, t=None, precision="fp32", final_level=-1, normal_level=-1, stack=None, kernels="auto",
+              iterations=None):
     import torch
     import paper_2201_09147_amd as nnm
     dev = torch.device("cuda", 0)
     own = stack is None
     if own:
         stack = nnm.load_siren_stack(scene, precision, 0)
-    p = nnm.TraceParams(scene.step_scale, scene.eps, scene.far, scene.max_steps, final_level, normal_level)
+    p = nnm.TraceParams(scene.step_scale, scene.eps, scene.far, scene.max_steps, final_level, normal_level,
+                        kernels=kernels, iterations=iterations)
     tt = None if t is None else torch.from_numpy(np.ascontiguousarray(t)).to(dev)
     out = nnm.render(stack, torch.from_numpy(o).to(dev), torch.from_numpy(v).to(dev), tt, p)
     torch.cuda.synchronize()
@@ -82,3 +84,34 @@ def sample_points(n, seed, d_in=3, shell=False):
     x = x.astype(np.float32)
     t = rng.uniform(0.0, 1.0, size=n).astype(np.float32)
     return x, t
+
+
+def sphere_eps_counts(o, v, deltas, s, cap=4000):
+    """Evaluations per level that eps-terminated tracing of the analytic sphere
+    needs without a budget: at level j the recursion
+    tau <- tau + s (|o + tau v| - 0.6 - delta_j) runs until its value d <= eps.
+    Also returns the smallest margin |d - eps| met at a level exit (to skip rays
+    whose count could depend on rounding)."""
+    o64, v64 = o.astype(np.float64), v.astype(np.float64)
+    n = o.shape[0]
+    m = len(deltas)
+    tau = np.zeros(n)
+    counts = np.zeros((n, m), np.int64)
+    margin = np.full(n, np.inf)
+    reach = np.ones(n, bool)
+    for j, delta in enumerate(deltas):
+        active = reach.copy()
+        k = np.zeros(n, np.int64)
+        for _ in range(cap):
+            if not active.any():
+                break
+            p = o64 + tau[:, None] * v64
+            d = np.sqrt(np.sum(p * p, axis=1)) - 0.6 - delta
+            k = np.where(active, k + 1, k)
+            tau = np.where(active, tau + s.step_scale * d, tau)
+            reach &= ~(active & (tau > s.far))
+            done = active & (d <= s.eps)
+            margin = np.where(active, np.minimum(margin, np.abs(d - s.eps)), margin)
+            active &= ~done & (tau <= s.far)
+        counts[:, j] = k
+    return counts, reach, margin

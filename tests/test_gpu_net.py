@@ -116,7 +116,7 @@ def test_empty_and_single_point():
     ("anim16_1024sq", "fp32", [(1, 0)]),
 ])
 def test_sup_abs_diff_matches_oracle_on_the_same_points(name, precision, pairs):
-    """nnm_sup_abs_diff (sampled |f_a - f_b|_inf, Sec. 4.2) against the oracle's
+    """nnm_sup_abs_diff (sampled |f_a - f_b|_inf, Sec. 3.3) against the oracle's
     float64 maximum over exactly the points the device drew (splitmix64)."""
     import torch
     import paper_2201_09147_amd as nnm
@@ -138,3 +138,38 @@ def test_sup_abs_diff_matches_oracle_on_the_same_points(name, precision, pairs):
     assert all(d > 0 for d in deltas) and all(deltas[i] > deltas[i + 1] for i in range(len(deltas) - 1))
     stack.close()
     del torch
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_sup_abs_err_matches_oracle_on_the_same_points(precision):
+    """nnm_sup_abs_err (sampled |f - f_level|_inf against a known SDF, the bound
+    of Proposition 2, Sec. 3.3) against the oracle's float64 maximum over exactly
+    the points the device drew.  Against the sphere |x| - 0.6 the difference is
+    the small network term a N (about 1e-3); against the torus it is of order
+    0.5, so both ends of the range are covered."""
+    import paper_2201_09147_amd as nnm
+    from nnm_inputs.sampling import box_points
+    from nnm_inputs.torus import torus_sdf
+    s = ni.make_scene("stack3_512sq")
+    stack = nnm.load_siren_stack(s, precision, 0)
+    n, seed, lo, hi = (1 << 16) + 77, 4321, -1.0, 1.0
+    x, _ = box_points(seed, n, lo, hi)
+    x64 = x.astype(np.float64)
+    refs = {"sphere": (0.6, 0.0, np.sqrt(np.sum(x64 * x64, axis=1)) - 0.6),
+            "torus": (0.5, 0.2, torus_sdf(x64))}
+    for level in range(3):
+        f = orc.scene_eval(s, level, x64, None, grad=False)
+        for shape, (a, b, sdf) in refs.items():
+            got = nnm.nnm_sup_abs_err(stack, level, shape, a, b, n, seed, lo, hi)
+            ref = float(np.max(np.abs(f - sdf)))
+            tol = 2e-6 + 1e-4 * ref if precision == "fp32" else 2e-6 + 3e-2 * ref
+            print(f"{precision} level {level} sup|{shape} - f| gpu {got:.6e} oracle {ref:.6e}")
+            assert abs(got - ref) <= tol
+    deltas, sups = nnm.capacity_thresholds(stack, "sphere", 0.6, n=n, seed=seed, margin=0.0)
+    assert all(deltas[i] > deltas[i + 1] for i in range(2))
+    assert deltas == nnm.nnm_nesting_thresholds(2, sups)
+    with pytest.raises(nnm.NnmError):
+        nnm.nnm_sup_abs_err(stack, 0, "torus", 0.5, 0.0, n, seed, lo, hi)
+    with pytest.raises(nnm.NnmError):
+        nnm.nnm_sup_abs_err(stack, 3, "sphere", 0.6, 0.0, n, seed, lo, hi)
+    stack.close()

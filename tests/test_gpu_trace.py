@@ -236,15 +236,13 @@ def test_edge_cases():
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
-def test_weight_stationary_matches_streaming(precision, monkeypatch):
+def test_weight_stationary_matches_streaming(precision):
     """The (256,2) level runs the weight-stationary kernels in bf16/fp16; the
-    streaming kernels (NNM_NO_WS=1) compute the same sums in another K order."""
+    streaming kernels (kernels="streaming") compute the same sums in another K order."""
     s = ni.make_scene("stack3_512sq").with_size(384, 256)
     o, v, _ = s.rays()
     ws = gpu_trace(s, o, v, precision=precision)
-    monkeypatch.setenv("NNM_NO_WS", "1")
-    st = gpu_trace(s, o, v, precision=precision)
-    monkeypatch.delenv("NNM_NO_WS")
+    st = gpu_trace(s, o, v, precision=precision, kernels="streaming")
     both = (ws["hit"] == 1) & (st["hit"] == 1)
     assert np.mean(ws["hit"] == st["hit"]) >= 0.9995
     assert np.abs(ws["depth"][both] - st["depth"][both]).max() <= 2e-4
@@ -287,4 +285,93 @@ def test_concurrent_streams_share_a_stack(precision):
         for out, r in zip(outs, ref):
             for key in ("depth", "hit", "normal", "steps", "status"):
                 assert torch.equal(out[key], r[key]), key
+    stack.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_budget_per_level_matches_oracle(precision):
+    """Algorithm 1's per-level budget on the GPU: on the analytic sphere (all
+    amplitudes 0) each ray's per-level counts k_j are known; with budgets from
+    min k - 1 to max k + 1 (so k_j - 1, k_j and k_j + 1 all occur) hit/miss,
+    status and every level's count equal the oracle's on the rays whose exits
+    are not within float32 rounding of eps.  fp32 runs the streaming tile on
+    every level, bf16 the weight-stationary kernel on the (256,2) level."""
+    from tests.parity import sphere_eps_counts
+    s = ni.make_scene("stack3_512sq").with_size(48, 40).with_amplitudes([0.0, 0.0, 0.0])
+    o, v, _ = s.rays()
+    deltas = [s.levels[0].delta, s.levels[1].delta, 0.0]
+    need, reach, margin = sphere_eps_counts(o, v, deltas, s)
+    keep = reach & (margin > 5e-6) & (need.max(axis=1) <= 40)
+    o, v, need = np.ascontiguousarray(o[keep]), np.ascontiguousarray(v[keep]), need[keep]
+    kmax = need.max(axis=1)
+    assert keep.sum() > 300
+    for budget in range(int(kmax.min()) - 1, int(kmax.max()) + 2):
+        s.max_steps = budget
+        g = gpu_trace(s, o, v, precision=precision)
+        r = orc.trace(s, o, v)
+        assert np.array_equal(r["hit"] == 1, kmax <= budget)
+        assert np.array_equal(g["hit"], r["hit"]), budget
+        assert np.array_equal(g["status"], r["status"]), budget
+        assert np.array_equal(g["steps"], r["steps"]), budget
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_nonfinite_values_match_oracle(precision):
+    """The NONFINITE path: a stack (32,1) |> (64,1) |> 4-D (256,2) with a static
+    centre, and rays whose time is NaN on every 7th ray and NaN origins on every
+    11th.  A NaN origin fails at level 0's first evaluation; a NaN time only
+    reaches the 4-D last level, so those rays trace levels 0-1 normally and fail
+    at their first level-2 evaluation (the weight-stationary kernel in bf16).
+    Status and per-level counts of those rays equal the oracle's exactly, and
+    the other rays pass the usual gates."""
+    base = ni.make_scene("stack3_512sq").with_size(96, 80)
+    fine4 = ni.make_scene("anim16_1024sq").levels[1]
+    levels = [base.levels[0], base.levels[1], ni.SceneLevel(fine4.net, fine4.amplitude, 0.0)]
+    s = ni.Scene("mixed_4d", levels, 96, 80)
+    o, v, _ = base.rays()
+    o = o.copy()
+    n = o.shape[0]
+    t = np.full(n, 0.25, np.float32)
+    t[::7] = np.nan
+    o[3::11, 0] = np.nan
+    g = gpu_trace(s, o, v, t, precision=precision)
+    r = orc.trace(s, o, v, t)
+    bad_o = np.zeros(n, bool)
+    bad_o[3::11] = True
+    assert np.all(r["status"][bad_o] == orc.ST_NONFINITE) and np.all(r["steps"][bad_o] == [1, 0, 0])
+    late = np.zeros(n, bool)
+    late[::7] = True
+    late &= ~bad_o & ((r["status"] & orc.ST_NONFINITE) != 0)
+    assert late.sum() > 20 and np.all(r["steps"][late][:, 2] == 1)
+    nf = bad_o | late
+    assert np.array_equal(g["status"][nf], r["status"][nf])
+    assert np.array_equal(g["steps"][nf], r["steps"][nf])
+    assert np.all(g["hit"][nf] == 0) and np.all(np.isinf(g["depth"][nf])) and np.all(g["normal"][nf] == 0)
+    keep = ~np.isnan(t) & ~bad_o
+    st = compare({k: val[keep] for k, val in g.items()}, {k: val[keep] for k, val in r.items()})
+    _report(f"non-finite mix {precision}", st)
+    (check_fp32 if precision == "fp32" else check_lowp)(st)
+
+
+def test_time_dependent_levels_require_times():
+    """A stack whose levels read the time (4-D net, moving centre) refuses
+    t = NULL with E_INVAL before any launch; a static 3-D stack accepts it."""
+    import torch
+    dev = torch.device("cuda", 0)
+    s = ni.make_scene("anim16_1024sq")
+    stack = nnm.load_siren_stack(s, "fp32", 0)
+    z = torch.zeros((4, 3), device=dev)
+    for call in (lambda: nnm.render(stack, z, z),
+                 lambda: nnm.analytic_normal(stack, 1, z, None, torch.empty(4, device=dev), torch.empty((4, 3), device=dev)),
+                 lambda: nnm.analytic_normal(stack, 0, z, None, torch.empty(4, device=dev), torch.empty((4, 3), device=dev)),
+                 lambda: nnm.neural_normal_map(stack, 1, z, None)):
+        with pytest.raises(nnm.NnmError) as e:
+            call()
+        assert e.value.code == -1 and "time" in str(e.value)
+    stack.close()
+    s3 = ni.make_scene("stack3_512sq")
+    stack = nnm.load_siren_stack(s3, "fp32", 0)
+    out = nnm.render(stack, z, torch.tensor([[0.0, 0.0, -1.0]] * 4, device=dev))
+    torch.cuda.synchronize()
+    assert out["hit"].shape == (4,)
     stack.close()

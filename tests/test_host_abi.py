@@ -171,3 +171,60 @@ def test_write_net_file_roundtrip_and_errors(lib, tmp_path):
         nnm.nnm_write_net_file(str(tmp_path / "no_such_dir" / "x.nnmw"), net.d_in, net.width, net.n_sine, flat)
     assert e.value.code == -9
     assert not (tmp_path / "bad.nnmw").exists()
+
+
+def _band(c, delta):
+    """[|f| <= delta] for f(x) = |x| - 0.6 + c, as an interval of radii."""
+    return (0.6 - c - delta, 0.6 - c + delta)
+
+
+def _nested(bands):
+    """Eq.(1): each band lies inside the band before it."""
+    return all(bands[i - 1][0] <= bands[i][0] + 1e-15 and bands[i][1] <= bands[i - 1][1] + 1e-15
+               for i in range(1, len(bands)))
+
+
+def test_nesting_thresholds_prop1_and_prop2(lib):
+    """Propositions 1 and 2 (Sec. 3.3) on radially offset spheres
+    f_i(x) = |x| - 0.6 + c_i, whose sup differences are exact: |f_i - f_j| = |c_i - c_j|
+    everywhere, and |f - f_i| = |c_i| against f = |x| - 0.6.  The bands
+    [|f_i| <= delta_i] are radius intervals, so Eq.(1)'s inclusion is checked in
+    closed form.  Offsets of alternating sign attain the bounds, so the thresholds
+    are tight: dropping any term, or shifting an index, breaks an inclusion."""
+    rng = np.random.default_rng(5)
+    for m in (2, 3, 5, 8):
+        for _ in range(20):
+            mag = rng.uniform(0.001, 0.05, m)
+            c = mag * np.where(np.arange(m) % 2 == 0, 1.0, -1.0)
+            # Proposition 2: bounds against f are |c_i|
+            d2 = nnm.nnm_nesting_thresholds(2, list(np.abs(c)))
+            assert _nested([_band(c[i], d2[i]) for i in range(m)])
+            # tight: every inclusion holds with equality at one end
+            for i in range(1, m):
+                lo_gap = _band(c[i], d2[i])[0] - _band(c[i - 1], d2[i - 1])[0]
+                hi_gap = _band(c[i - 1], d2[i - 1])[1] - _band(c[i], d2[i])[1]
+                assert min(lo_gap, hi_gap) <= 1e-15
+            # Proposition 1: bounds between consecutive members are |c_i - c_{i-1}|
+            sup1 = [0.0] + [abs(c[i] - c[i - 1]) for i in range(1, m)]
+            d1 = nnm.nnm_nesting_thresholds(1, sup1)
+            assert _nested([_band(c[i], d1[i]) for i in range(m)])
+            assert d1[m - 1] == sup1[m - 1]
+            # a margin raises every bound: thresholds grow, bands stay nested
+            d1m = nnm.nnm_nesting_thresholds(1, sup1, 1e-3)
+            assert all(a > b for a, b in zip(d1m, d1))
+            assert _nested([_band(c[i], d1m[i]) for i in range(m)])
+    # closed forms of the recursions for m = 3
+    assert np.allclose(nnm.nnm_nesting_thresholds(2, [0.1, 0.05, 0.01]), [0.27, 0.12, 0.06], rtol=0, atol=1e-15)
+    assert np.allclose(nnm.nnm_nesting_thresholds(1, [9.0, 0.05, 0.01]), [0.07, 0.02, 0.01], rtol=0, atol=1e-15)
+
+
+def test_nesting_thresholds_errors(lib):
+    for prop, sup, margin in [(3, [0.1, 0.1], 0.0), (1, [0.1], 0.0), (2, [0.1] * 9, 0.0),
+                              (2, [0.1, -0.1], 0.0), (2, [0.1, float("nan")], 0.0), (1, [0.0, 0.1], -1.0),
+                              (1, [0.0, float("inf")], 0.0)]:
+        with pytest.raises(nnm.NnmError) as e:
+            nnm.nnm_nesting_thresholds(prop, sup, margin)
+        assert e.value.code == -1, (prop, sup, margin)
+    # Proposition 1 does not read sup[0]
+    assert nnm.nnm_nesting_thresholds(1, [float("nan"), 0.1]) == [0.2, 0.1]
+

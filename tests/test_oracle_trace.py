@@ -18,6 +18,7 @@ import pytest
 
 import nnm_inputs as ni
 from oracle import tracing as T
+from tests.parity import sphere_eps_counts
 
 
 def _sphere_hit(o, v, c=None, r=0.6):
@@ -288,37 +289,6 @@ def test_fixed_iterations_sphere_recursion():
         np.testing.assert_allclose(r["normal"][hit], p / np.linalg.norm(p, axis=1, keepdims=True), atol=1e-12)
 
 
-def _sphere_eps_counts(o, v, deltas, s, cap=4000):
-    """Evaluations per level that eps-terminated tracing of the analytic sphere
-    needs without a budget: at level j the recursion
-    tau <- tau + s (|o + tau v| - 0.6 - delta_j) runs until its value d <= eps.
-    Also returns the smallest margin |d - eps| met at a level exit (to skip rays
-    whose count could depend on rounding)."""
-    o64, v64 = o.astype(np.float64), v.astype(np.float64)
-    n = o.shape[0]
-    m = len(deltas)
-    tau = np.zeros(n)
-    counts = np.zeros((n, m), np.int64)
-    margin = np.full(n, np.inf)
-    reach = np.ones(n, bool)
-    for j, delta in enumerate(deltas):
-        active = reach.copy()
-        k = np.zeros(n, np.int64)
-        for _ in range(cap):
-            if not active.any():
-                break
-            p = o64 + tau[:, None] * v64
-            d = np.sqrt(np.sum(p * p, axis=1)) - 0.6 - delta
-            k = np.where(active, k + 1, k)
-            tau = np.where(active, tau + s.step_scale * d, tau)
-            reach &= ~(active & (tau > s.far))
-            done = active & (d <= s.eps)
-            margin = np.where(active, np.minimum(margin, np.abs(d - s.eps)), margin)
-            active &= ~done & (tau <= s.far)
-        counts[:, j] = k
-    return counts, reach, margin
-
-
 def test_budget_pins_on_axis_closed_form():
     """Algorithm 1's per-level budget on the analytic sphere, from a closed form.
     A ray from (0,0,2.5) straight at the centre meets the level-j band at
@@ -356,7 +326,7 @@ def test_budget_pins_recursion_many_rays():
     s = ni.make_scene("stack3_512sq").with_size(40, 40).with_amplitudes([0.0, 0.0, 0.0])
     o, v, _ = s.rays()
     deltas = [s.levels[0].delta, s.levels[1].delta, 0.0]
-    need, reach, margin = _sphere_eps_counts(o, v, deltas, s)
+    need, reach, margin = sphere_eps_counts(o, v, deltas, s)
     keep = reach & (margin > 1e-9) & (need.max(axis=1) <= 40)
     o, v, need = o[keep], v[keep], need[keep]
     kmax = need.max(axis=1)
