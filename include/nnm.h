@@ -135,9 +135,17 @@ int nnm_validate_stack(const nnm_stack_desc* desc, int precision);
    base_sphere.  Returns NNM_OK and writes *bound. */
 int nnm_level_lipschitz_bound(const nnm_level_desc* level, int base_sphere, double* bound);
 
-/* Validates desc, packs the weights for `precision` and uploads them to
-   `device`.  The descriptor may be freed afterwards.  *out is owned by the
-   caller and released with free_siren_stack. */
+/* Loads a nested sequence f_1 |> ... |> f_m (Sec. 3.2: each level a neural SDF
+   whose delta_j-neighbourhood contains the next level's, Eq.(1); each network
+   the sine MLP of Eq.(2), Sec. 5.1) for tracing on `device`.
+   Validates desc as nnm_validate_stack does (nothing is allocated on a
+   failure), packs the weights for `precision` (float32 masters; bf16 / fp16
+   copies of the hidden layers, rounded to nearest even) and uploads them
+   once.  The descriptor and its parameter arrays may be freed afterwards.
+   *out is owned by the caller and released with free_siren_stack; a loaded
+   stack is immutable, so calls on several streams may share it.
+   Errors: NNM_E_INVAL (null out, bad device), the validation codes,
+   NNM_E_NOMEM, NNM_E_DEVICE. */
 int load_siren_stack(const nnm_stack_desc* desc, int precision, int device, nnm_stack** out);
 
 /* Frees the library-owned device copies of a stack; NULL is a no-op. */
@@ -241,10 +249,18 @@ typedef struct {
 int fit_create(const nnm_net_shape* shape, const float* params, int device, int64_t max_points, nnm_fit** out);
 void fit_free(nnm_fit* fit);
 
-/* One step: loss, gradient through the double backward, Adam update.  loss4:
-   device [4] out (the four mean terms), or NULL.  Asynchronous on `stream`.
-   Every sum over points runs over a fixed partition in a fixed order, so the
-   same state and batch give bitwise the same step on the same device. */
+/* One step of fitting a neural SDF (Sec. 3.3, "MLPs for a single surface":
+   each network is trained to a known SDF with the eikonal approach the paper
+   cites; the loss terms are those of nnm_fit_batch, with the normal term on
+   the unit gradient): the loss, its parameter gradient by reverse mode through
+   the value and the analytic gradient of Sec. 5.1 (a double backward), and an
+   Adam update.  batch: device arrays of at most max_points points in total;
+   loss4: device [4] out (the four mean terms), or NULL.  Asynchronous on
+   `stream`.  Every sum over points runs over a fixed partition in a fixed
+   order, so the same state and batch give bitwise the same step on the same
+   device.  Errors: NNM_E_INVAL (null, a negative count, more than max_points
+   points, lr or eps not positive, a beta outside [0, 1)),
+   NNM_E_UNSUPPORTED (a 4-D network: the loss takes 3-D points), NNM_E_DEVICE. */
 int fit_step(nnm_fit* fit, const nnm_fit_batch* batch, const nnm_adam* opt, float* loss4, void* stream);
 
 /* Loss terms and gradient only (no update): dparams device [P] out. */

@@ -15,6 +15,12 @@ Workloads (rays; levels as (width, k) in the paper's notation):
   stack3_4096sq       4096x4096; the same stack
   anim16_1024sq       16 frames x 1024x1024, t = i/16; (64,1) s5 a=.005 on x - c(t)
                       |> 4-D (256,2) s4 a=.02, delta_1 = 0.05, rho = 0.2
+  stack2_64x1_128x2_512sq
+                      512x512; (64,1) s31 a=.015 |> (128,2) s32 a=.02, delta = 0.05
+                      (the widths of the paper's animated example, static here)
+  stack3_bigarg_512sq 512x512; the three-level stack with its (256,2) level's hidden
+                      biases shifted by 300 revolutions (bias_turns = 300): the same
+                      function, with hidden sine arguments near 300 revolutions
   fit_torus_256x2     fitting a (256,2) net (seed 6) to the torus; rendered at 1080p
   table3_*            the rows of the paper's Table 3 at 512x512, traced with fixed
                       iteration counts (TABLE3_ROWS gives the counts and which net is
@@ -133,6 +139,14 @@ def make_scene(name: str) -> Scene:
         return Scene(name, _stack3(), 1920, 1080)
     if name == "stack3_4096sq":
         return Scene(name, _stack3(), 4096, 4096)
+    if name == "stack2_64x1_128x2_512sq":
+        levels = [SceneLevel(siren_init(31, 3, 64, 2, 0.015), 0.015, 0.05),
+                  SceneLevel(siren_init(32, 3, 128, 3, 0.02), 0.02, 0.0)]
+        return Scene(name, levels, 512, 512)
+    if name == "stack3_bigarg_512sq":
+        levels = _stack3()
+        levels[2] = SceneLevel(siren_init(3, 3, 256, 3, 0.02, bias_turns=300), 0.02, 0.0)
+        return Scene(name, levels, 512, 512)
     if name == "anim16_1024sq":
         levels = [
             SceneLevel(siren_init(5, 3, 64, 2, 0.005), 0.005, 0.05, follow_center=True),
@@ -148,4 +162,4 @@ def make_scene(name: str) -> Scene:
 
 
 WORKLOADS = ["single_64x1_128sq", "stack3_512sq", "stack3_1080p", "stack3_4096sq",
-             "anim16_1024sq", "fit_torus_256x2"] + list(TABLE3_ROWS)
+             "stack2_64x1_128x2_512sq", "stack3_bigarg_512sq", "anim16_1024sq", "fit_torus_256x2"] + list(TABLE3_ROWS)

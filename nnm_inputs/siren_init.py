@@ -23,6 +23,12 @@ float32):
 * hidden:   W ~ U(-sqrt(6/H), sqrt(6/H)), b ~ U(-1/sqrt(H), 1/sqrt(H))
 * output:   W ~ U(-sqrt(6/H)/30, sqrt(6/H)/30), b ~ U(-1/sqrt(H), 1/sqrt(H))
 
+Optional ``bias_turns = k`` adds 2 pi k to every hidden-layer bias (layers
+1..n_sine-1).  sin is 2 pi periodic, so the network stays the same function up
+to the float32 rounding of the shifted biases, while its hidden pre-activations
+grow to about k revolutions: a stand-in for trained networks whose hidden
+arguments are large, exercising a kernel's sine argument reduction.
+
 Lipschitz safety: the scene function is f = |x - c| - r0 + a * N(x), so
 |grad f| <= 1 + a * Lip(N) and Lip(N) <= sigma(W_K) * prod_{i<K} sigma(W_i)
 (|sin'| <= 1; for layer 0 only the spatial columns count).  The output layer
@@ -109,7 +115,7 @@ def lipschitz_product_bound(layers, spatial_cols: int = 3) -> float:
 
 
 def siren_init(seed: int, d_in: int, width: int, n_sine: int, amplitude: float,
-               lip_max: float = LIP_MAX, normalise: bool = True) -> SirenNet:
+               lip_max: float = LIP_MAX, normalise: bool = True, bias_turns: int = 0) -> SirenNet:
     """Draw a SIREN with the scheme in the module docstring; float32 result."""
     if n_sine < 1:
         raise ValueError("a SIREN needs at least one sine layer")
@@ -124,6 +130,8 @@ def siren_init(seed: int, d_in: int, width: int, n_sine: int, amplitude: float,
             w_lim, b_lim, scale = np.sqrt(6.0 / fan_in) / OMEGA0, 1.0 / np.sqrt(fan_in), 1.0
         W = rng.uniform(-w_lim, w_lim, size=(fan_out, fan_in)) * scale
         b = rng.uniform(-b_lim, b_lim, size=(fan_out,)) * scale
+        if 0 < i < n_sine:
+            b = b + 2.0 * np.pi * bias_turns
         layers64.append((W, b))
     layers = [(W.astype(np.float32), b.astype(np.float32)) for (W, b) in layers64]
     if normalise and amplitude > 0.0:

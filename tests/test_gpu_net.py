@@ -17,7 +17,18 @@ from tests.parity import NET_REL_L2, rel_l2, sample_points
 pytestmark = pytest.mark.gpu
 
 CASES = [("single_64x1_128sq", 0), ("stack3_512sq", 0), ("stack3_512sq", 1), ("stack3_512sq", 2),
-         ("anim16_1024sq", 0), ("anim16_1024sq", 1)]
+         ("anim16_1024sq", 0), ("anim16_1024sq", 1),
+         # (256,3): four sine layers; (256,1): two; width 128; hidden arguments near
+         # 300 revolutions (the range-reduced sine of every kernel family)
+         ("table3_256x3", 0), ("table3_64x1_256x1", 1), ("stack2_64x1_128x2_512sq", 0),
+         ("stack2_64x1_128x2_512sq", 1), ("stack3_bigarg_512sq", 2)]
+
+# float32 keeps 24 bits, so a sine argument near K = 300 revolutions carries up to
+# 2^-24 * 300 = 1.8e-5 revolutions (1.1e-4 rad) of rounding per operation; a few
+# roundings per argument give activation errors near 3e-4 rad against activations
+# of rms 0.7, i.e. a relative L2 error of N up to about 1e-3 on top of each form's
+# own error.
+BIGARG_EXTRA = 2e-3
 
 
 def _torch():
@@ -73,7 +84,7 @@ def test_net_value_and_gradient(name, level, precision):
     # GPU subtracts a float32 c(t); compare against that input in float64)
     inp = _net_input(scene, level, x, t)
     rv, rg = orc.net_eval(scene.levels[level].net, inp)
-    tol = NET_REL_L2[precision]
+    tol = NET_REL_L2[precision] + (BIGARG_EXTRA if name == "stack3_bigarg_512sq" else 0.0)
     ev, eg = rel_l2(val, rv), rel_l2(grad, rg)
     print(f"{name} level {level} {precision}: rel L2 N {ev:.2e} grad {eg:.2e} |N|max {np.abs(rv).max():.3e}")
     assert ev <= tol and eg <= tol

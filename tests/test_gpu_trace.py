@@ -375,3 +375,47 @@ def test_time_dependent_levels_require_times():
     torch.cuda.synchronize()
     assert out["hit"].shape == (4,)
     stack.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("row", sorted(ni.TABLE3_ROWS))
+def test_table3_rows_fixed_iterations(row, precision):
+    """Every row of the Table-3 replica (fixed iteration counts; the last net of a
+    nested row gives the normals only) against the oracle's fixed-iteration mode,
+    at 128x128: (256,3) alone, (64,1) alone, (64,1) |> (256,k) for k = 1, 2, 3, and
+    the three-net row (20 steps on (64,1), 5 on (256,1), normals of (256,3))."""
+    nets, its, normal = ni.TABLE3_ROWS[row]
+    s = ni.make_scene(row).with_size(128, 128)
+    o, v, _ = s.rays()
+    final = len(its) - 1
+    g = gpu_trace(s, o, v, precision=precision, final_level=final, normal_level=normal, iterations=its)
+    r = orc.trace(s, o, v, final_level=final, normal_level=normal, iterations=its)
+    st = compare(g, r)
+    _report(f"table3 {row} {precision}", st)
+    (check_fp32 if precision == "fp32" else check_lowp)(st)
+    hit = g["hit"] == 1
+    assert st["common"] > 2000
+    assert np.all(g["steps"][hit][:, :final + 1] == np.array(its))
+
+
+@pytest.mark.parametrize("name,precision", [("stack2_64x1_128x2_512sq", "fp32"), ("stack2_64x1_128x2_512sq", "bf16"),
+                                            ("stack2_64x1_128x2_512sq", "fp16"),
+                                            ("table3_64x1_256x1", "fp32"), ("table3_64x1_256x1", "bf16"),
+                                            ("table3_64x1_256x3", "fp32"), ("table3_64x1_256x3", "bf16"),
+                                            ("stack3_bigarg_512sq", "fp32"), ("stack3_bigarg_512sq", "bf16"),
+                                            ("stack3_bigarg_512sq", "fp16")])
+def test_other_widths_and_depths_eps_mode(name, precision):
+    """Eps-terminated multiscale tracing with normals for the configurations the
+    validator accepts beyond the headline stack: width 128, (256,1) and (256,3)
+    fine levels (streaming tile in every form), and a (256,2) level whose hidden
+    sine arguments reach 300 revolutions (the range-reduced streaming tile in
+    fp32, the range-reduced weight-stationary kernels in bf16 / fp16)."""
+    s = ni.make_scene(name).with_size(192, 160)
+    o, v, _ = s.rays()
+    for final, normal in ((len(s.levels) - 1, len(s.levels) - 1), (len(s.levels) - 2, len(s.levels) - 1)):
+        g = gpu_trace(s, o, v, precision=precision, final_level=final, normal_level=normal)
+        r = orc.trace(s, o, v, final_level=final, normal_level=normal)
+        st = compare(g, r)
+        _report(f"{name} final {final} normal {normal} {precision}", st)
+        (check_fp32 if precision == "fp32" else check_lowp)(st)
+        assert st["common"] > 3000
