@@ -32,10 +32,11 @@ def _hipcc():
     return "hipcc"
 
 
-def _compile(src: str, verbose: bool, defines=(), build_dir=BUILD_DIR) -> str:
+def _compile(src: str, verbose: bool, defines=(), build_dir=BUILD_DIR, host_flags=()) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *COMMON, *[f"-D{d}" for d in defines], "-x", "hip", "-c", path, "-o", obj]
+    host = [x for f in host_flags for x in ("-Xarch_host", f)]
+    cmd = [_hipcc(), *COMMON, *host, *[f"-D{d}" for d in defines], "-x", "hip", "-c", path, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     noise = "packed-fp32-ops"
     err = "\n".join(l for l in res.stderr.splitlines() if noise not in l and l.strip())
@@ -46,16 +47,18 @@ def _compile(src: str, verbose: bool, defines=(), build_dir=BUILD_DIR) -> str:
     return obj
 
 
-def build(verbose: bool = False, defines=(), out=LIB, build_dir=BUILD_DIR) -> str:
+def build(verbose: bool = False, defines=(), out=LIB, build_dir=BUILD_DIR, host_flags=(), link_flags=()) -> str:
     """Compile every source and link libnnm.so; returns the library path.
 
-    ``defines`` (e.g. ["NNM_RING_LOWP=6"]) and ``out`` build a variant."""
+    ``defines`` (e.g. ["NNM_RING_LOWP=6"]) and ``out`` build a variant;
+    ``host_flags`` go to the host compilation only (each after -Xarch_host),
+    ``link_flags`` to the link."""
     os.makedirs(build_dir, exist_ok=True)
     sources = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with cf.ThreadPoolExecutor(max_workers=min(len(sources), os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose, defines, build_dir), sources))
+        objs = list(ex.map(lambda s: _compile(s, verbose, defines, build_dir, host_flags), sources))
     tmp = out + ".tmp"
-    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, *link_flags, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")
