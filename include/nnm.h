@@ -174,6 +174,26 @@ int trace_rays(const nnm_stack* stack, const nnm_trace_params* params, int64_t n
                const float* v, const float* t, float* depth, uint8_t* hit, float* normal,
                uint8_t* steps, uint8_t* status, void* stream);
 
+/* Largest n that trace_rays_noalloc accepts (a 1920 x 1080 frame fits). */
+#define NNM_NOALLOC_MAX_RAYS (1 << 21)
+
+/* trace_rays for callers that cannot allocate: code under HIP graph capture,
+   tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+   kernels and results as trace_rays, but it calls no hipMalloc, hipFree or
+   allocating routine: its scratch (ray queues, counters, status carrier;
+   about 19 MB) is a static device array of the library, one per GPU, which
+   each GPU the library runs on holds until the process ends.  Its address is
+   looked up on the first call on a device.
+   Every call on one GPU uses that GPU's one array: calls that may overlap in
+   time on one GPU (other streams, other threads, no ordering between them)
+   race and give wrong results; calls on one stream are ordered and safe.
+   Errors: those of trace_rays; NNM_E_INVAL for n > NNM_NOALLOC_MAX_RAYS or a
+   non-NULL params->profiler (a profiler creates events); NNM_E_DEVICE when
+   the array's address cannot be looked up. */
+int trace_rays_noalloc(const nnm_stack* stack, const nnm_trace_params* params, int64_t n,
+                       const float* o, const float* v, const float* t, float* depth, uint8_t* hit,
+                       float* normal, uint8_t* steps, uint8_t* status, void* stream);
+
 /* Analytic gradient of one scene function (Eq.(3)-(4) with the G_i form of
    Alg. 2, one shared forward for the three tangent columns):
      x      device [n][3] points; t device [n] or NULL

@@ -7,7 +7,7 @@ Device arrays are torch tensors on the stack's device; streams are torch
 streams (default: the current stream).
 
 Entry points (same names as the C ABI in include/nnm.h):
-  load_siren_stack, free_siren_stack, trace_rays, analytic_normal,
+  load_siren_stack, free_siren_stack, trace_rays, trace_rays_noalloc, analytic_normal,
   nnm_net_eval, nnm_sup_abs_diff, nnm_sup_abs_err, nnm_nesting_thresholds,
   neural_normal_map, nnm_grid_values,
   nnm_mesh_extract, nnm_validate_stack, nnm_read_net_file, nnm_sync
@@ -34,6 +34,8 @@ from ._binding import (  # noqa: F401
     load_siren_stack,
     free_siren_stack,
     trace_rays,
+    trace_rays_noalloc,
+    NOALLOC_MAX_RAYS,
     analytic_normal,
     nnm_net_eval,
     nnm_sup_abs_diff,

@@ -89,6 +89,7 @@ def load_library(path: Optional[str] = None):
         "nnm_stack_levels": ([P], c_int),
         "nnm_stack_precision": ([P], c_int),
         "trace_rays": ([P, P, c_int64, P, P, P, P, P, P, P, P, P], c_int),
+        "trace_rays_noalloc": ([P, P, c_int64, P, P, P, P, P, P, P, P, P], c_int),
         "analytic_normal": ([P, c_int, c_int64, P, P, P, P, P], c_int),
         "nnm_net_eval": ([P, c_int, c_int64, P, P, P, P, P], c_int),
         "nnm_sup_abs_diff": ([P, c_int, c_int, c_int64, ctypes.c_uint64, ctypes.c_float, ctypes.c_float, P, P], c_int),
@@ -268,7 +269,7 @@ class Profiler:
         _check(load_library().nnm_profiler_reset(self._h))
 
     def report(self):
-        """List of dicts (kind 'trace'/'normal', level, width, kernel, launches, total_ms)."""
+        """List of dicts (kind 'trace'/'normal', level, width, kernel, variant, launches, total_ms)."""
         r = _ProfileReport()
         _check(load_library().nnm_profiler_report(self._h, ctypes.cast(ctypes.byref(r), c_void_p)))
         names = {("trace", 0): "k_trace_level", ("trace", 1): "k_trace_ws",
@@ -277,7 +278,7 @@ class Profiler:
         for i in range(r.n_entries):
             kind = ("trace", "normal")[r.kind[i]]
             out.append({"kind": kind, "level": r.level[i], "width": r.width[i],
-                        "kernel": names[(kind, r.variant[i])],
+                        "kernel": names[(kind, r.variant[i])], "variant": int(r.variant[i]),
                         "launches": int(r.launches[i]), "total_ms": float(r.total_ms[i])})
         return out
 
@@ -350,6 +351,20 @@ def _stream_ptr(stream, device):
 def trace_rays(stack: Stack, params: TraceParams, o, v, t, depth, hit, normal=None, steps=None, status=None,
                stream=None):
     """Multiscale sphere tracing into caller-allocated tensors (see include/nnm.h)."""
+    _trace_call("trace_rays", stack, params, o, v, t, depth, hit, normal, steps, status, stream)
+
+
+def trace_rays_noalloc(stack: Stack, params: TraceParams, o, v, t, depth, hit, normal=None, steps=None,
+                       status=None, stream=None):
+    """trace_rays with the library's static per-GPU scratch: no device allocation
+    (at most NNM_NOALLOC_MAX_RAYS rays; calls that overlap on one GPU race)."""
+    _trace_call("trace_rays_noalloc", stack, params, o, v, t, depth, hit, normal, steps, status, stream)
+
+
+NOALLOC_MAX_RAYS = 1 << 21
+
+
+def _trace_call(entry, stack, params, o, v, t, depth, hit, normal, steps, status, stream):
     import torch
     n = int(o.shape[0]) if hasattr(o, "shape") else 0
     dev = stack.device
@@ -364,8 +379,8 @@ def trace_rays(stack: Stack, params: TraceParams, o, v, t, depth, hit, normal=No
         _dev_ptr(status, torch.uint8, (n,), "status", dev),
     ]
     cp = params.c(stack.m)
-    _check(load_library().trace_rays(stack.handle, ctypes.cast(ctypes.byref(cp), c_void_p), n, *args,
-                                     _stream_ptr(stream, dev)))
+    fn = getattr(load_library(), entry)
+    _check(fn(stack.handle, ctypes.cast(ctypes.byref(cp), c_void_p), n, *args, _stream_ptr(stream, dev)))
 
 
 def analytic_normal(stack: Stack, level: int, x, t, value, grad, stream=None):

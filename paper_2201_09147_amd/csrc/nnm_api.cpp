@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -156,7 +157,7 @@ uint16_t to_f16_rne(float x) {
   return b;
 }
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -503,10 +504,23 @@ static bool level_reads_time(const nnm_stack* s, int j) {
 int nnm_stack_levels(const nnm_stack* s) { return s ? s->m : -1; }
 int nnm_stack_precision(const nnm_stack* s) { return s ? s->precision : -1; }
 
-int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const float* o, const float* v,
-               const float* t, float* depth, uint8_t* hit, float* normal, uint8_t* steps, uint8_t* status,
-               void* stream) {
-  g_err.clear();
+// Scratch of one trace_rays call: counters (head and out count per level), two
+// ping-pong queues, and the status carrier when the caller passes none.
+// cnt[2j], cnt[2j+1]: spare / rays out of level j; heads of level j at
+// cnt + 64 + j * kSegments * kHeadStride.
+struct TraceScratch {
+  static constexpr int n_cnt = 64 + kMaxLevels * kSegments * kHeadStride;
+  size_t off_qa, off_qb, off_st, total;
+  constexpr TraceScratch(int64_t n, bool status) : off_qa(0), off_qb(0), off_st(0), total(0) {
+    off_qa = align256((size_t)n_cnt * 4);
+    off_qb = off_qa + align256((size_t)n * 4);
+    off_st = off_qb + align256((size_t)n * 4);
+    total = off_st + (status ? 0 : align256((size_t)n));
+  }
+};
+
+static int trace_validate(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const float* o, const float* v,
+                          const float* t, float* depth, uint8_t* hit, float* normal) {
   if (!s || !p) return fail(NNM_E_INVAL, "null stack or params");
   if (n < 0) return fail(NNM_E_INVAL, "n = %lld < 0", (long long)n);
   if (n > (int64_t)INT_MAX - (1 << 24)) return fail(NNM_E_INVAL, "n = %lld too large", (long long)n);
@@ -533,28 +547,22 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
     if (normal && level_reads_time(s, p->normal_level))
       return fail(NNM_E_INVAL, "null t, but normal level %d depends on the time", p->normal_level);
   }
-  DeviceGuard guard(s->device);
-  if (!guard.ok) return fail(NNM_E_DEVICE, "hipSetDevice(%d) failed", s->device);
-  hipStream_t st = (hipStream_t)stream;
+  return NNM_OK;
+}
+
+// The launch sequence of one validated trace_rays call (n > 0) on the current
+// device, with its scratch at wb (laid out by TraceScratch).  Every launch is
+// a kernel (the counters are cleared by a fill kernel, not a memset).
+static int trace_launch(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const float* o, const float* v,
+                        const float* t, float* depth, uint8_t* hit, float* normal, uint8_t* steps, uint8_t* status,
+                        char* wb, hipStream_t st) {
+  const TraceScratch sc(n, status != nullptr);
   const int L = p->final_level + 1;
-  // Scratch: counters (head and out count per level), two ping-pong queues,
-  // and the status carrier when the caller passes none.
-  // cnt[2j], cnt[2j+1]: spare / rays out of level j; heads of level j at
-  // cnt + 64 + j * kSegments * kHeadStride.
-  const int n_cnt = 64 + kMaxLevels * kSegments * kHeadStride;
-  const size_t off_cnt = 0;
-  const size_t off_qa = align256((size_t)n_cnt * 4);
-  const size_t off_qb = off_qa + align256((size_t)n * 4);
-  const size_t off_st = off_qb + align256((size_t)n * 4);
-  const size_t total = off_st + (status ? 0 : align256((size_t)n));
-  void* ws = nullptr;
-  hipError_t e = hipMallocAsync(&ws, total, st);
-  if (e != hipSuccess) return fail(NNM_E_NOMEM, "hipMallocAsync(%zu): %s", total, hipGetErrorString(e));
-  char* wb = (char*)ws;
-  int* cnt = (int*)(wb + off_cnt);
-  int* q[2] = {(int*)(wb + off_qa), (int*)(wb + off_qb)};
-  uint8_t* stat = status ? status : (uint8_t*)(wb + off_st);
+  int* cnt = (int*)wb;
+  int* q[2] = {(int*)(wb + sc.off_qa), (int*)(wb + sc.off_qb)};
+  uint8_t* stat = status ? status : (uint8_t*)(wb + sc.off_st);
   int rc = NNM_OK;
+  hipError_t e;
   if ((e = launch_zero_ints(cnt, 64 + L * kSegments * kHeadStride, st)) != hipSuccess)
     rc = hip_fail(e, "zeroing counters");
   for (int j = 0; j < L && rc == NNM_OK; ++j) {
@@ -623,8 +631,68 @@ int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const f
       if ((e = launch_normal(nl.width, s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "normal pass");
     }
   }
+  return rc;
+}
+
+// Scratch of trace_rays_noalloc: one static array per GPU, sized for the
+// largest call it accepts (NNM_NOALLOC_MAX_RAYS rays, status carrier included).
+// In host code `scratch` only names the symbol: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+constexpr size_t kNoAllocScratchBytes = TraceScratch(NNM_NOALLOC_MAX_RAYS, false).total;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev` (resolved on the
+// first call for that device).
+static int noalloc_scratch(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(NNM_E_DEVICE, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail(NNM_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return NNM_OK;
+}
+
+int trace_rays(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const float* o, const float* v,
+               const float* t, float* depth, uint8_t* hit, float* normal, uint8_t* steps, uint8_t* status,
+               void* stream) {
+  g_err.clear();
+  int rc = trace_validate(s, p, n, o, v, t, depth, hit, normal);
+  if (rc != NNM_OK || n == 0) return rc;
+  DeviceGuard guard(s->device);
+  if (!guard.ok) return fail(NNM_E_DEVICE, "hipSetDevice(%d) failed", s->device);
+  hipStream_t st = (hipStream_t)stream;
+  const TraceScratch sc(n, status != nullptr);
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, sc.total, st);
+  if (e != hipSuccess) return fail(NNM_E_NOMEM, "hipMallocAsync(%zu): %s", sc.total, hipGetErrorString(e));
+  rc = trace_launch(s, p, n, o, v, t, depth, hit, normal, steps, status, (char*)ws, st);
   if ((e = hipFreeAsync(ws, st)) != hipSuccess && rc == NNM_OK) rc = hip_fail(e, "hipFreeAsync");
   return rc;
+}
+
+int trace_rays_noalloc(const nnm_stack* s, const nnm_trace_params* p, int64_t n, const float* o, const float* v,
+                       const float* t, float* depth, uint8_t* hit, float* normal, uint8_t* steps, uint8_t* status,
+                       void* stream) {
+  g_err.clear();
+  int rc = trace_validate(s, p, n, o, v, t, depth, hit, normal);
+  if (rc != NNM_OK) return rc;
+  if (n > NNM_NOALLOC_MAX_RAYS)
+    return fail(NNM_E_INVAL, "n = %lld exceeds the %d rays of the static scratch", (long long)n, NNM_NOALLOC_MAX_RAYS);
+  if (p->profiler) return fail(NNM_E_INVAL, "a profiler creates events; trace_rays_noalloc takes none");
+  if (n == 0) return NNM_OK;
+  DeviceGuard guard(s->device);
+  if (!guard.ok) return fail(NNM_E_DEVICE, "hipSetDevice(%d) failed", s->device);
+  char* wb = nullptr;
+  if ((rc = noalloc_scratch(s->device, &wb)) != NNM_OK) return rc;
+  return trace_launch(s, p, n, o, v, t, depth, hit, normal, steps, status, wb, (hipStream_t)stream);
 }
 
 static int points_common(const nnm_stack* s, int level, int64_t n, const float* x, const float* t, float* value,

@@ -45,6 +45,13 @@ def _levels():
     return nnm.levels_from_scene(ni.make_scene("stack3_512sq"))
 
 
+def test_noalloc_entry_point_validates_on_the_host(lib):
+    """trace_rays_noalloc refuses a null stack before touching a device."""
+    import ctypes
+    rc = lib.trace_rays_noalloc(None, None, ctypes.c_int64(16), None, None, None, None, None, None, None, None, None)
+    assert rc == -1 and b"null" in lib.nnm_last_error()
+
+
 def test_validate_accepts_workload_scenes(lib):
     for name in ["single_64x1_128sq", "stack3_512sq", "anim16_1024sq"]:
         s = ni.make_scene(name)
