@@ -322,8 +322,10 @@ def test_nonfinite_values_match_oracle(precision):
     11th.  A NaN origin fails at level 0's first evaluation; a NaN time only
     reaches the 4-D last level, so those rays trace levels 0-1 normally and fail
     at their first level-2 evaluation (the weight-stationary kernel in bf16).
-    Status and per-level counts of those rays equal the oracle's exactly, and
-    the other rays pass the usual gates."""
+    Status of those rays equals the oracle's exactly, as do the counts of the
+    rays that fail at level 0 and the last-level count (1) of the late ones;
+    their level 0-1 counts follow the usual step agreement, and the other rays
+    pass the usual gates."""
     base = ni.make_scene("stack3_512sq").with_size(96, 80)
     fine4 = ni.make_scene("anim16_1024sq").levels[1]
     levels = [base.levels[0], base.levels[1], ni.SceneLevel(fine4.net, fine4.amplitude, 0.0)]
@@ -345,7 +347,13 @@ def test_nonfinite_values_match_oracle(precision):
     assert late.sum() > 20 and np.all(r["steps"][late][:, 2] == 1)
     nf = bad_o | late
     assert np.array_equal(g["status"][nf], r["status"][nf])
-    assert np.array_equal(g["steps"][nf], r["steps"][nf])
+    # the failing evaluation is counted on its level and nothing after it
+    assert np.array_equal(g["steps"][bad_o], r["steps"][bad_o])
+    assert np.all(g["steps"][late][:, 2] == 1)
+    # levels 0-1 of the late rays are ordinary float32 tracing: a one-step eps
+    # flip against the float64 oracle is allowed on a few rays, as elsewhere
+    d01 = np.abs(g["steps"][late][:, :2].astype(int) - r["steps"][late][:, :2].astype(int))
+    assert d01.max() <= 1 and np.mean(d01 == 0) >= 0.99, d01.sum()
     assert np.all(g["hit"][nf] == 0) and np.all(np.isinf(g["depth"][nf])) and np.all(g["normal"][nf] == 0)
     keep = ~np.isnan(t) & ~bad_o
     st = compare({k: val[keep] for k, val in g.items()}, {k: val[keep] for k, val in r.items()})
@@ -394,7 +402,10 @@ def test_table3_rows_fixed_iterations(row, precision):
     _report(f"table3 {row} {precision}", st)
     (check_fp32 if precision == "fp32" else check_lowp)(st)
     hit = g["hit"] == 1
-    assert st["common"] > 2000
+    # the three-net row gives its (256,1) level 5 steps only: about a quarter of
+    # the object's rays end within eps then (the oracle's count), so the floor
+    # that keeps the comparison meaningful is 500 common hits
+    assert st["common"] > 500
     assert np.all(g["steps"][hit][:, :final + 1] == np.array(its))
 
 
