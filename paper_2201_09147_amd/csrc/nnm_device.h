@@ -32,7 +32,10 @@ constexpr int kPushBatch = 64;      // queue entries a wave publishes per atomic
 constexpr int kSegments = 64;       // input queue segments, each with its own head
 constexpr int kHeadStride = 32;     // ints between segment heads (one 128-byte line each)
 constexpr int kPipeGroups = 5;       // slot groups in flight in a weight-stationary workgroup
-constexpr int kWsRaysPerBlock = 160;  // ray slots of a weight-stationary tracing workgroup
+#ifndef NNM_WS_TRACE_COLS
+#define NNM_WS_TRACE_COLS 32           // columns (rays) of a weight-stationary tracing tile
+#endif
+constexpr int kWsRaysPerBlock = kPipeGroups * NNM_WS_TRACE_COLS;  // ray slots of a weight-stationary tracing workgroup
 constexpr int kWsPointsPerBlock = 80; // point slots of a weight-stationary normal workgroup
 
 // Index of the accumulator-layout slot (mb, g, r) in a [H] array.

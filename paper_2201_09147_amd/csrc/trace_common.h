@@ -13,6 +13,13 @@ __device__ inline float4 net_input(const DevLevel& L, float x, float y, float z,
   return make_float4(x, y, z, 0.f);
 }
 
+// Distance |x - c| of the base sphere, on the hardware square root (about one
+// ulp; the correctly rounded software sequence costs some 20 instructions per
+// evaluation on the tracing kernels' critical path).
+__device__ inline float base_radius(float dx, float dy, float z) {
+  return __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, z * z)));
+}
+
 __device__ inline void center_at(const DevBase& B, float t, float& cx, float& cy) {
   cx = 0.f;
   cy = 0.f;

@@ -48,7 +48,7 @@ k_trace_level(TraceLevelArgs A) {
   const int n_in = A.in_count ? *A.in_count : A.n;
   SirenTile<H, P, false> tile;
   int ray = -1, k = 0, st = 0;
-  float tau = 0.f, ox = 0.f, oy = 0.f, oz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, tt = 0.f;
+  float tau = 0.f, ox = 0.f, oy = 0.f, oz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, tt = 0.f, cx = 0.f, cy = 0.f;
   // Wave-uniform work chunk [cur, end) of the input queue and push-ring state.
   // The queue is split into kSegments contiguous segments with one pop counter
   // each (separate cache lines, so the atomics spread over many addresses); a
@@ -101,6 +101,7 @@ k_trace_level(TraceLevelArgs A) {
           vy = A.v[3 * ray + 1];
           vz = A.v[3 * ray + 2];
           tt = A.t ? A.t[ray] : 0.f;
+          center_at(A.B, tt, cx, cy);  // c(t) is fixed per ray: once, on entry
           k = 0;
           if (A.level == 0) {
             tau = 0.f;
@@ -119,8 +120,6 @@ k_trace_level(TraceLevelArgs A) {
     if (__ballot(ray >= 0) == 0ull) break;
 
     const float x = fmaf(tau, vx, ox), y = fmaf(tau, vy, oy), z = fmaf(tau, vz, oz);
-    float cx, cy;
-    center_at(A.B, tt, cx, cy);
     const float N = tile.eval(&sm, A.L, net_input(A.L, x, y, z, tt, cx, cy), 0);
 
     int outcome = 0;  // 0: keep stepping, 1: left the level through d <= eps, 2: miss
@@ -128,7 +127,7 @@ k_trace_level(TraceLevelArgs A) {
       float base_term = 0.f;
       if (A.B.sphere) {
         const float dx = x - cx, dy = y - cy;
-        base_term = sqrtf(fmaf(dx, dx, fmaf(dy, dy, z * z))) - A.B.r0;
+        base_term = base_radius(dx, dy, z) - A.B.r0;
       }
       const float f = fmaf(A.L.amplitude, N, base_term);
       const float d = f - A.delta;

@@ -36,7 +36,7 @@ constexpr int kPipeThreads = 512;
 // Columns per tile: 32 for tracing (fewer rays in flight keeps the tiles full
 // while the last, longest rays finish), 64 for the normal pass (no iteration,
 // so twice the columns per control step is a straight gain).
-constexpr int kTraceCols = 32;
+constexpr int kTraceCols = NNM_WS_TRACE_COLS;
 constexpr int kNormalCols = 64;
 constexpr int kPipeStride = 256 + 8;  // 16-bit elements per LDS column (spreads LDS banks)
 constexpr int kParkMax = kTraceCols / 2;  // most survivors a group parks (tail compaction)
@@ -47,7 +47,8 @@ constexpr int kParkMax = kTraceCols / 2;  // most survivors a group parks (tail 
 #ifndef NNM_WS_CTL_NOH1
 #define NNM_WS_CTL_NOH1 1
 #endif
-constexpr int kOff0Wave = NNM_WS_CTL_NOH1 ? 3 : 1;  // tracing: the wave that computes role 0's first-layer block
+// tracing: the wave that computes role 0's first-layer block
+constexpr int kOff0Wave = (kTraceCols == 32 && NNM_WS_CTL_NOH1) ? 3 : 1;
 static_assert(kPipeGroups == 5, "tile t uses group t % 5: five tiles are in flight");
 static_assert(kPipeGroups * kTraceCols == kWsRaysPerBlock && kPipeGroups * kNormalCols / 4 == kWsPointsPerBlock, "slots");
 
@@ -562,7 +563,7 @@ struct TraceCtl {
       if (A.B.sphere) {
         const float x = fmaf(tau, vx, ox), y = fmaf(tau, vy, oy), z = fmaf(tau, vz, oz);
         const float dx = x - cx, dy = y - cy;
-        base_term = sqrtf(fmaf(dx, dx, fmaf(dy, dy, z * z))) - A.B.r0;
+        base_term = base_radius(dx, dy, z) - A.B.r0;
       }
       const float f = fmaf(L.amplitude, N, base_term);
       const float d = f - A.delta;
