@@ -105,7 +105,8 @@ def run_form(scene, precision, o, v, t, steps, warmup, final_level=-1, normal_le
         avg_ms = e["total_ms"] / max(e["launches"], 1)
         kernels.append({"kind": e["kind"], "kernel": e["kernel"], "level": e["level"], "width": e["width"],
                         "avg_ms": avg_ms,
-                        "evals": units, "hidden_flops": flops,
+                        "evals": units,
+                        "hidden_flops": flops,
                         "tflops": flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0})
     res = {"precision": precision, "workload": scene.name, "ms_per_step": ms, "rays_per_s": n / (ms * 1e-3), "hits": hits, "timing": timing,
            "evals_per_level": evals, "kernels": kernels,
@@ -318,13 +319,69 @@ PAPER_TABLE3_FPS = {"table3_256x3": 19.8, "table3_64x1": 128.8, "table3_64x1_256
                     "table3_64x1_256x2": 53.0, "table3_64x1_256x3": 41.6, "table3_64x1_256x1_256x3": 39.1}
 
 
-def run_table3(precisions, steps=20, warmup=3):
+def errors_vs_oracle(out, ref):
+    """Mask agreement, max depth error and normal angles of GPU outputs against
+    the oracle on the same rays."""
+    import numpy as np
+    hit, rhit = out["hit"] == 1, ref["hit"] == 1
+    both = hit & rhit
+    a64, b64 = out["normal"][both].astype(np.float64), ref["normal"][both]
+    ang = np.degrees(np.arctan2(np.linalg.norm(np.cross(a64, b64), axis=1), np.sum(a64 * b64, axis=1)))
+    return {"rays": int(hit.size), "mask_agreement": round(float(np.mean(hit == rhit)), 6),
+            "depth_max_abs_err": float(np.abs(out["depth"][both] - ref["depth"][both]).max()) if both.any() else 0.0,
+            "normal_angle_mean_deg": float(ang.mean()) if both.any() else 0.0,
+            "normal_angle_max_deg": float(ang.max()) if both.any() else 0.0, "common_hits": int(both.sum())}
+
+
+def run_extra_workload(name, forms, steps, warmup, rows_every, frames=None):
+    """Another configuration in the default run, timed like the headline frame
+    (one trace_rays call over all its rays), with its errors against the oracle
+    on every rows_every-th row (of the listed frames)."""
+    import numpy as np
+    import torch
+    import nnm_inputs as ni
+    from oracle import tracing as orc
+    scene = ni.make_scene(name)
+    o_np, v_np, t_np = scene.rays()
+    dev = torch.device("cuda", 0)
+    o, v = torch.from_numpy(o_np).to(dev), torch.from_numpy(v_np).to(dev)
+    t = torch.from_numpy(t_np).to(dev) if t_np is not None else None
+    n = o_np.shape[0]
+    log(f"[{name}] {n} rays")
+    runs = {f: run_form(scene, f, o, v, t, steps, warmup) for f in forms}
+    del o, v, t
+    per_frame = scene.width * scene.height
+    fr = np.asarray(frames if frames is not None else [0])
+    rows = np.arange(rows_every // 2, scene.height, rows_every)
+    idx = (fr[:, None, None] * per_frame + rows[None, :, None] * scene.width
+           + np.arange(scene.width)[None, None, :]).reshape(-1)
+    c0 = time.perf_counter()
+    ref = orc.trace(scene, o_np[idx], v_np[idx], None if t_np is None else t_np[idx])
+    oracle_s = time.perf_counter() - c0
+    res = {"workload": name, "rays": n, "oracle_sample": f"every {rows_every}th row of frames {fr.tolist()} "
+                                                      f"({idx.size} rays, {oracle_s:.1f} s on the host)",
+           "forms": {}}
+    for f, r in runs.items():
+        err = errors_vs_oracle({k: val[idx] for k, val in r["outputs"].items()}, ref)
+        res["forms"][f] = {"rays_per_s": round(r["rays_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                           "timing": r["timing"], "hits": r["hits"], "evals_per_level": r["evals_per_level"],
+                           "roofline": roofline(r),
+                           "kernels": [{k2: (round(v2, 5) if isinstance(v2, float) else v2) for k2, v2 in k.items()}
+                                       for k in r["kernels"]],
+                           "errors_vs_oracle": err}
+        log(f"[{name} {f}] {r['rays_per_s'] / 1e6:.1f} Mrays/s; vs oracle {err}")
+    return res
+
+
+def run_table3(precisions, steps=20, warmup=3, oracle_rows_every=8):
     """The rows of Table 3 at 512x512 in fixed-iteration mode (20 steps on the
     first net, 5 on the second in the last row; the last net of a nested row
     gives the normals only), timed per call with HIP events."""
+    import numpy as np
     import torch
     import nnm_inputs as ni
     import paper_2201_09147_amd as nnm
+    from oracle import tracing as orc
     dev = torch.device("cuda", 0)
     rows = []
     for name, (nets, iters, normal) in ni.TABLE3_ROWS.items():
@@ -352,7 +409,19 @@ def run_table3(precisions, steps=20, warmup=3):
             row[prec] = {"ms_median": round(ms, 4), "fps": round(1e3 / ms, 1),
                          "mrays_per_s": round(o_np.shape[0] / (ms * 1e-3) / 1e6, 1),
                          "hits": int(out["hit"].to(torch.int64).sum().item())}
+            if oracle_rows_every:
+                if "_ref" not in row:
+                    rws = np.arange(oracle_rows_every // 2, scene.height, oracle_rows_every)
+                    idx = (rws[:, None] * scene.width + np.arange(scene.width)[None, :]).reshape(-1)
+                    row["_idx"] = idx
+                    row["_ref"] = orc.trace(scene, o_np[idx], v_np[idx], final_level=final, normal_level=normal,
+                                            iterations=iters)
+                idx = row["_idx"]
+                g = {k: val.cpu().numpy()[idx] for k, val in out.items() if val is not None}
+                row[prec]["errors_vs_oracle"] = errors_vs_oracle(g, row["_ref"])
             stack.close()
+        row.pop("_ref", None)
+        row.pop("_idx", None)
         log(f"[table3] {name}: " + ", ".join(f"{p_} {row[p_]['fps']} FPS" for p_ in precisions)
             + f" (paper, RTX 3090: {row['paper_fps_rtx3090']} FPS)")
         rows.append(row)
@@ -625,8 +694,10 @@ def main():
                     help="also fit (32,1), (64,1), (256,2) to the torus, nest them by Prop. 1 and render at 1080p")
     ap.add_argument("--nesting", action="store_true",
                     help="also estimate sup |f_j - f_(j-1)| of the stack over 1e8 points (Prop. 1 thresholds)")
-    ap.add_argument("--table3", action="store_true",
-                    help="also time the rows of the paper's Table 3 at 512^2 in fixed-iteration mode")
+    ap.add_argument("--no-table3", action="store_true",
+                    help="skip the rows of the paper's Table 3 at 512^2 in fixed-iteration mode")
+    ap.add_argument("--no-extra-workloads", action="store_true",
+                    help="skip the 4096^2 stress frame and the 16-frame animated call")
     ap.add_argument("--fit-full", action="store_true",
                     help="also run the whole 2000-step fit, its quality and a 1080p render of the fitted net")
     ap.add_argument("--mesh", action="store_true",
@@ -678,7 +749,12 @@ def main():
         fit["full"] = run_fit_full()
     nesting = run_nesting(args.workload, args.precision) if args.nesting else None
     capacity = run_capacity() if args.capacity else None
-    table3 = run_table3([f for f in ("fp32", "bf16") if f in forms] or [args.precision]) if args.table3 else None
+    table3 = None if args.no_table3 else run_table3([f for f in ("fp32", "bf16") if f in forms] or [args.precision])
+    extra = None
+    if not args.no_extra_workloads and args.workload == "stack3_1080p":
+        xf = [f for f in ("fp32", "bf16") if f in forms] or [args.precision]
+        extra = {"stack3_4096sq": run_extra_workload("stack3_4096sq", xf, 5, 2, 64),
+                 "anim16_1024sq": run_extra_workload("anim16_1024sq", xf, 5, 2, 64, frames=[0, 5, 10, 15])}
     mesh = [run_mesh(args.workload, f) for f in (("fp32", "bf16") if "fp32" in forms else (args.precision,))] \
         if args.mesh else None
 
@@ -782,6 +858,7 @@ def main():
         "fit": fit,
         "nnm_variant": nnm_block,
         "table3_fixed_iterations": table3,
+        "extra_workloads": extra,
         "mesh_normal_mapping": mesh,
         "nesting": nesting,
         "capacity_sequence": capacity,
