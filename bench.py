@@ -558,46 +558,34 @@ def _clip_to_box(o_np, v_np):
     return t_in, t_out
 
 
-def run_capacity(steps=2000):
+def run_capacity(steps=4000, omega0=10.0):
     """Capacity-sequence training (Sec. 3.3): the three shapes of the nested
-    stack, (32,1), (64,1) and (256,2), fitted to the torus on the same batches;
-    nesting thresholds from the sampled sup |torus - f_j| by Proposition 2;
-    then multiscale sphere tracing of the trained stack at 1080p against single-
+    stack, (32,1), (64,1) and (256,2), fitted to the torus on the same batches
+    (first-layer frequency omega0 for all three: a smoother starting basis than
+    30 keeps the fits' sup error off the corners of the training box); nesting
+    thresholds from the sampled sup |torus - f_j| by Proposition 2; then
+    multiscale sphere tracing of the trained stack at 1080p against single-
     level tracing of the finest net and against the exact torus."""
-    import concurrent.futures as cf
     import numpy as np
     import torch
     import nnm_inputs as ni
     import paper_2201_09147_amd as nnm
+    from paper_2201_09147_amd import capacity as cap
     scene = ni.make_scene("fit_torus_256x2")
     ns, nu, lr = scene.extra["n_surf"], scene.extra["n_unif"], scene.extra["lr"]
     dev = torch.device("cuda", 0)
     # width, sine layers, init seed, Adam lr (the small nets learn slowly at 1e-4)
-    shapes = [(32, 2, 11, 1e-3), (64, 2, 12, 1e-3), (256, 3, 6, lr)]
-    nets = [ni.siren_init(seed, 3, w, k, 1.0, normalise=False) for w, k, seed, _ in shapes]
-    fits = [nnm.Fit(3, n_.width, n_.n_sine, n_.flat(), 0, ns + nu) for n_ in nets]
-    losses = [torch.empty(4, dtype=torch.float32, device=dev) for _ in nets]
-    ahead = 8
-    with cf.ThreadPoolExecutor(4) as pool:
-        futs = {i: pool.submit(ni.torus_batch, i, ns, nu) for i in range(min(ahead, steps))}
-        t0 = time.perf_counter()
-        for i in range(steps):
-            b = futs.pop(i).result()
-            if i + ahead < steps:
-                futs[i + ahead] = pool.submit(ni.torus_batch, i + ahead, ns, nu)
-            bt = tuple(torch.from_numpy(a).to(dev) for a in b)
-            for f, l, sh in zip(fits, losses, shapes):
-                f.step_adam(*bt, lr=sh[3], loss4=l)
-            if i % 500 == 0 or i == steps - 1:
-                log(f"[capacity] step {i}: " + " | ".join(
-                    f"({n_.width},{n_.n_sine - 1}) {sum(l.cpu().tolist()):.4f}" for n_, l in zip(nets, losses)))
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-    fitted = [ni.SirenNet(3, n_.width, n_.n_sine, ni.unflatten_params(f.params(), 3, n_.width, n_.n_sine))
-              for n_, f in zip(nets, fits)]
-    final_loss = [[round(float(x), 6) for x in l.cpu().numpy()] for l in losses]
-    for f in fits:
-        f.close()
+    shapes = [(32, 2, 11, 1e-3), (64, 2, 12, 1e-3), (256, 3, 13, lr)]
+    nets = [ni.siren_init(seed, 3, w, k, 1.0, normalise=False, omega0=omega0) for w, k, seed, _ in shapes]
+    t0 = time.perf_counter()
+    params, last = cap.fit_sequence(nets, [sh[3] for sh in shapes], steps, lambda i: ni.torus_batch(i, ns, nu),
+                                    max_points=ns + nu,
+                                    log=lambda i, ls: log(f"[capacity] step {i}: " + " | ".join(
+                                        f"({n_.width},{n_.n_sine - 1}) {l:.4f}" for n_, l in zip(nets, ls))))
+    wall = time.perf_counter() - t0
+    fitted = [ni.SirenNet(3, n_.width, n_.n_sine, ni.unflatten_params(p_, 3, n_.width, n_.n_sine))
+              for n_, p_ in zip(nets, params)]
+    final_loss = [[round(float(x), 6) for x in l] for l in last]
 
     def make(levels, deltas):
         lv = [ni.SceneLevel(n_, 1.0, d) for n_, d in zip(levels, deltas)]
@@ -606,9 +594,10 @@ def run_capacity(steps=2000):
     # thresholds on the training domain [-1, 1]^3: Proposition 2 from the sampled
     # sup |torus - f_j| (the nets approximate one known SDF), and Proposition 1
     # from the sampled sup |f_j - f_(j-1)| beside it; the render uses Proposition 2
+    d_p2, sups_p2 = cap.nest_by_proposition2([nnm.LevelSpec(3, n_.width, n_.n_sine, n_.flat(), 1.0, 0.0)
+                                              for n_ in fitted], "torus", ni.torus.R_MAJOR, ni.torus.R_MINOR,
+                                             1 << 26, 77, -1.0, 1.0, margin=1e-3)
     probe = nnm.load_siren_stack(make(fitted, [1.0, 0.5, 0.0]), "fp32", 0, lipschitz_max=0.0)
-    d_p2, sups_p2 = nnm.capacity_thresholds(probe, "torus", ni.torus.R_MAJOR, ni.torus.R_MINOR, 1 << 26, 77, -1.0, 1.0,
-                                            margin=1e-3)
     d_p1, sups_p1 = nnm.nesting_thresholds(probe, 1 << 26, 77, -1.0, 1.0, margin=1e-3)
     probe.close()
     deltas = d_p2[:2]
@@ -619,6 +608,13 @@ def run_capacity(steps=2000):
     inbox = np.flatnonzero(t_out > t_in)
     o = torch.from_numpy((o_np[inbox] + t_in[inbox, None] * v_np[inbox]).astype(np.float32)).to(dev)
     v = torch.from_numpy(np.ascontiguousarray(v_np[inbox])).to(dev)
+    # Algorithm 1 expects rays to start outside the coarse band |f_1| <= delta_1
+    probe = nnm.load_siren_stack(make(fitted, deltas + [0.0]), "fp32", 0, lipschitz_max=0.0)
+    f1 = torch.empty(o.shape[0], dtype=torch.float32, device=dev)
+    nnm.nnm_net_eval(probe, 0, o, None, f1, None)
+    start_outside = float((f1 > deltas[0]).float().mean().item())
+    probe.close()
+    log(f"[capacity] rays starting outside the coarse band: {start_outside:.4f}")
     rows = np.arange(0, 1080, 8)
     idx = (rows[:, None] * 1920 + np.arange(1920)[None, :]).reshape(-1)
     rhit, rtau = _torus_trace_exact(o_np[idx], v_np[idx], scene.step_scale, scene.eps, scene.far)
@@ -661,7 +657,8 @@ def run_capacity(steps=2000):
     for r in out_rows.values():
         r.pop("_depth")
         r.pop("_hit")
-    return {"steps": steps, "wall_s": round(wall, 2), "nets": ["(32,1)", "(64,1)", "(256,2)"],
+    return {"steps": steps, "wall_s": round(wall, 2), "nets": ["(32,1)", "(64,1)", "(256,2)"], "omega0": omega0,
+            "rays_starting_outside_coarse_band": start_outside,
             "adam_lr": [sh[3] for sh in shapes],
             "final_loss4": final_loss, "sup_abs_err_vs_torus": sups_p2, "deltas_prop2": d_p2,
             "sup_abs_diff": sups_p1, "deltas_prop1": d_p1, "renders_1080p": out_rows}
@@ -691,7 +688,7 @@ def main():
                     help="skip the neural-normal-mapping variant (trace to level m-2, normals of level m-1)")
     ap.add_argument("--fit-steps", type=int, default=10, help="fitting steps to time (0: skip)")
     ap.add_argument("--capacity", action="store_true",
-                    help="also fit (32,1), (64,1), (256,2) to the torus, nest them by Prop. 1 and render at 1080p")
+                    help="also fit (32,1), (64,1), (256,2) to the torus, nest them by Prop. 2 and render at 1080p")
     ap.add_argument("--nesting", action="store_true",
                     help="also estimate sup |f_j - f_(j-1)| of the stack over 1e8 points (Prop. 1 thresholds)")
     ap.add_argument("--no-table3", action="store_true",

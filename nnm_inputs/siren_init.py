@@ -115,19 +115,24 @@ def lipschitz_product_bound(layers, spatial_cols: int = 3) -> float:
 
 
 def siren_init(seed: int, d_in: int, width: int, n_sine: int, amplitude: float,
-               lip_max: float = LIP_MAX, normalise: bool = True, bias_turns: int = 0) -> SirenNet:
-    """Draw a SIREN with the scheme in the module docstring; float32 result."""
+               lip_max: float = LIP_MAX, normalise: bool = True, bias_turns: int = 0,
+               omega0: float = OMEGA0) -> SirenNet:
+    """Draw a SIREN with the scheme in the module docstring; float32 result.
+
+    ``omega0`` is the first layer's frequency scale (30 unless a caller asks
+    for a smoother starting basis, as the coarse nets of a capacity sequence
+    do); the output layer's 1/omega0 factor follows it."""
     if n_sine < 1:
         raise ValueError("a SIREN needs at least one sine layer")
     rng = np.random.default_rng(seed)
     layers64 = []
     for i, (fan_out, fan_in) in enumerate(layer_shapes(d_in, width, n_sine)):
         if i == 0:
-            w_lim, b_lim, scale = 1.0 / fan_in, 1.0 / np.sqrt(fan_in), OMEGA0
+            w_lim, b_lim, scale = 1.0 / fan_in, 1.0 / np.sqrt(fan_in), omega0
         elif i < n_sine:
             w_lim, b_lim, scale = np.sqrt(6.0 / fan_in), 1.0 / np.sqrt(fan_in), 1.0
         else:
-            w_lim, b_lim, scale = np.sqrt(6.0 / fan_in) / OMEGA0, 1.0 / np.sqrt(fan_in), 1.0
+            w_lim, b_lim, scale = np.sqrt(6.0 / fan_in) / omega0, 1.0 / np.sqrt(fan_in), 1.0
         W = rng.uniform(-w_lim, w_lim, size=(fan_out, fan_in)) * scale
         b = rng.uniform(-b_lim, b_lim, size=(fan_out,)) * scale
         if 0 < i < n_sine:
