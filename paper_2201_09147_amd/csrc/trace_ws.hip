@@ -209,24 +209,38 @@ __device__ inline void pipe_hidden(const PipeWeights<P>& W, const uint16_t* src,
   }
 }
 
-// sin of a team-1 wave's rows into the next layer's activations.
-// One 32-row block `blk` of the first hidden product with A read from LDS
-// (W_1 rows [32 blk, 32 blk + 32)); same k order as pipe_hidden.
+// The hidden product of a team-1 wave that also computes one of the control
+// wave's W_1 row blocks (A from LDS): three accumulator chains (the wave's two
+// row blocks and the LDS block) in one k loop share each B fragment and keep
+// the matrix pipe busy while the LDS operands arrive; same k order as
+// pipe_hidden.
 template <int C, int P>
-__device__ inline void pipe_hidden_lds(const uint4* wlds, int blk, const uint16_t* src, const float* bias,
-                                       f32x16_t (&acc)[(C / 32)], const PipeLane& pl) {
+__device__ inline void pipe_hidden3(const PipeWeights<P>& W, const uint4* wlds, int blk, const uint16_t* src,
+                                    const float* bias, f32x16_t (&acc)[(C / 32)][2], f32x16_t (&acc1)[(C / 32)],
+                                    int tw, const PipeLane& pl) {
   typedef HiddenOps<P> Ops;
   typedef typename Ops::frag_t frag_t;
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int b4 = 0; b4 < 4; ++b4) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      const float4 b = *(const float4*)&bias[64 * tw + 32 * rb + 8 * b4 + 4 * pl.g];
+#pragma unroll
+      for (int cb = 0; cb < (C / 32); ++cb) {
+        acc[cb][rb][4 * b4 + 0] = b.x;
+        acc[cb][rb][4 * b4 + 1] = b.y;
+        acc[cb][rb][4 * b4 + 2] = b.z;
+        acc[cb][rb][4 * b4 + 3] = b.w;
+      }
+    }
     const float4 b = *(const float4*)&bias[32 * blk + 8 * b4 + 4 * pl.g];
 #pragma unroll
     for (int cb = 0; cb < (C / 32); ++cb) {
-      acc[cb][4 * b4 + 0] = b.x;
-      acc[cb][4 * b4 + 1] = b.y;
-      acc[cb][4 * b4 + 2] = b.z;
-      acc[cb][4 * b4 + 3] = b.w;
+      acc1[cb][4 * b4 + 0] = b.x;
+      acc1[cb][4 * b4 + 1] = b.y;
+      acc1[cb][4 * b4 + 2] = b.z;
+      acc1[cb][4 * b4 + 3] = b.w;
     }
   }
 #pragma unroll
@@ -237,7 +251,11 @@ __device__ inline void pipe_hidden_lds(const uint4* wlds, int blk, const uint16_
     for (int cb = 0; cb < (C / 32); ++cb)
       b[cb] = *(const frag_t*)&src[(32 * cb + pl.j) * kPipeStride + 16 * ks + 8 * pl.g];
 #pragma unroll
-    for (int cb = 0; cb < (C / 32); ++cb) acc[cb] = Ops::mfma(a, b[cb], acc[cb]);
+    for (int cb = 0; cb < (C / 32); ++cb) {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) acc[cb][rb] = Ops::mfma(W.w[rb][ks], b[cb], acc[cb][rb]);
+      acc1[cb] = Ops::mfma(a, b[cb], acc1[cb]);
+    }
   }
 }
 
@@ -339,15 +357,15 @@ __device__ inline void pipe_team1_hidden(PipeSmem<C>& sm, const PipeWeights<P>& 
   if (sm.tlive[(s + 7) & 7]) {
     constexpr bool kNoH1 = C == 32 && !TAN && NNM_WS_CTL_NOH1;
     if (kNoH1 && wave == 0) return;
+    if (kNoH1 && (wave == 1 || wave == 2)) {
+      f32x16_t acc1[(C / 32)];
+      pipe_hidden3<C, P>(W, sm.w1lds, wave - 1, sm.act0[(s + 1) & 1], sm.bias[0], acc, acc1, wave & 3, pl);
+      pipe_store<C, P, TAN, RED>(acc, sm.act1[(s + 1) & 1], wave & 3, pl);
+      pipe_store_blk<C, P, TAN, RED>(acc1, sm.act1[(s + 1) & 1], wave - 1, pl);
+      return;
+    }
     pipe_hidden<C, P>(W, sm.act0[(s + 1) & 1], (TAN && pl.c) ? sm.zeros : sm.bias[0], acc, wave & 3, pl);
     pipe_store<C, P, TAN, RED>(acc, sm.act1[(s + 1) & 1], wave & 3, pl);
-    if constexpr (kNoH1) {
-      if (wave == 1 || wave == 2) {
-        f32x16_t acc1[(C / 32)];
-        pipe_hidden_lds<C, P>(sm.w1lds, wave - 1, sm.act0[(s + 1) & 1], sm.bias[0], acc1, pl);
-        pipe_store_blk<C, P, TAN, RED>(acc1, sm.act1[(s + 1) & 1], wave - 1, pl);
-      }
-    }
   }
 }
 
@@ -452,7 +470,10 @@ struct TraceCtl {
     s_ox = s_oy = s_oz = s_vx = s_vy = s_vz = s_tt = s_tau = 0.f;
     s_head = s_count = 0;
     cur = end = 0;
-    chunk = min(kChunk, max(64, (n_in / (8 * (int)gridDim.x)) & ~63));
+#ifndef NNM_WS_CHUNK_DIV
+#define NNM_WS_CHUNK_DIV 8
+#endif
+    chunk = min(kChunk, max(64, (n_in / (NNM_WS_CHUNK_DIV * (int)gridDim.x)) & ~63));
     seg_len = (n_in + kSegments - 1) / kSegments;
     seg = blockIdx.x % kSegments;
     seg_tries = 0;
@@ -704,10 +725,27 @@ struct TraceCtl {
   }
 };
 
-// One team's side of the tracing kernel; role 0 (team 1) runs the control.  The
-// two sides execute the same number of workgroup barriers.
+// One team's side of the tracing kernel; role 0 (team 1) runs the control and
+// holds no weights (its W_1 rows are in LDS), so its loop is separate and the
+// register budget of the evaluating roles does not include the control's
+// state.  Every wave executes the same number of workgroup barriers.
 template <int P, bool RED, bool TEAM2>
 __device__ inline void trace_body(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int wave, int lane) {
+  if (!TEAM2 && wave == 0 && NNM_WS_CTL_NOH1) {
+    TraceCtl ctl;
+    ctl.init(A);
+    ctl.top_up(A, lane);
+    __syncthreads();
+    ctl.step(sm, A, -1, lane);
+    __syncthreads();
+    for (int s = 0;; ++s) {
+      if (sm.stop[(s + 1) & 1]) break;
+      ctl.step(sm, A, s, lane);
+      __syncthreads();
+    }
+    ctl.flush(sm, A, lane);
+    return;
+  }
   PipeWeights<P> W;
   W.load(A.L, wave, lane, wave, wave == kOff0Wave ? 0 : -1);  // this role also computes the control wave's block
   const PipeLane pl = pipe_lane<false>(lane);
