@@ -506,10 +506,11 @@ int nnm_stack_precision(const nnm_stack* s) { return s ? s->precision : -1; }
 
 // Scratch of one trace_rays call: counters (head and out count per level), two
 // ping-pong queues, and the status carrier when the caller passes none.
-// cnt[2j], cnt[2j+1]: spare / rays out of level j; heads of level j at
-// cnt + 64 + j * kSegments * kHeadStride.
+// cnt[2j], cnt[2j+1]: rays out of level j in the back / front region of its
+// output queue; the pop heads of level j's input at cnt + 64 + (2j + r) *
+// kSegments * kHeadStride (r = 0 back, 1 front region).
 struct TraceScratch {
-  static constexpr int n_cnt = 64 + kMaxLevels * kSegments * kHeadStride;
+  static constexpr int n_cnt = 64 + 2 * kMaxLevels * kSegments * kHeadStride;
   size_t off_qa, off_qb, off_st, total;
   constexpr TraceScratch(int64_t n, bool status) : off_qa(0), off_qb(0), off_st(0), total(0) {
     off_qa = align256((size_t)n_cnt * 4);
@@ -563,7 +564,7 @@ static int trace_launch(const nnm_stack* s, const nnm_trace_params* p, int64_t n
   uint8_t* stat = status ? status : (uint8_t*)(wb + sc.off_st);
   int rc = NNM_OK;
   hipError_t e;
-  if ((e = launch_zero_ints(cnt, 64 + L * kSegments * kHeadStride, st)) != hipSuccess)
+  if ((e = launch_zero_ints(cnt, 64 + 2 * L * kSegments * kHeadStride, st)) != hipSuccess)
     rc = hip_fail(e, "zeroing counters");
   for (int j = 0; j < L && rc == NNM_OK; ++j) {
     const auto& lv = s->levels[j];
@@ -580,10 +581,20 @@ static int trace_launch(const nnm_stack* s, const nnm_trace_params* p, int64_t n
     a.status = stat;
     a.in_queue = j == 0 ? nullptr : q[(j - 1) & 1];
     a.in_count = j == 0 ? nullptr : cnt + 2 * (j - 1) + 1;
-    a.in_heads = cnt + 64 + j * kSegments * kHeadStride;
+    a.in_count_long = j == 0 ? nullptr : cnt + 2 * (j - 1);
+    a.in_heads = cnt + 64 + (2 * j + 1) * kSegments * kHeadStride;
+    a.in_heads_long = cnt + 64 + 2 * j * kSegments * kHeadStride;
     const bool is_final = (j == L - 1);
     a.out_queue = (!is_final || normal) ? q[j & 1] : nullptr;
     a.out_count = cnt + 2 * j + 1;
+    // slow rays go to the back region of the next level's queue (not for the
+    // normal pass, which has no iterations, nor in fixed-iteration mode, where
+    // every ray takes the same count, nor to or from a width-32 level, whose
+    // kernel keeps one region)
+    a.out_count_long = (!is_final && p->mode == 0 && lv.width != 32 && s->levels[j + 1].width != 32)
+                           ? cnt + 2 * j
+                           : nullptr;
+    a.long_steps = kLongSteps;
     a.n = (int)n;
     a.level = j;
     a.m = s->m;

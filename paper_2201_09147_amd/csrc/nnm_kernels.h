@@ -23,10 +23,14 @@ struct TraceLevelArgs {
   uint8_t* steps;       // [n][m], may be null
   uint8_t* status;      // never null (library scratch when the caller passes null)
   const int* in_queue;  // null: ray ids 0..n-1
-  const int* in_count;  // null: n
-  int* in_heads;        // kSegments pop counters, kHeadStride ints apart, zeroed
+  const int* in_count;  // entries in the front region of in_queue; null: n
+  const int* in_count_long;  // entries in the back region (admitted first); null: none
+  int* in_heads;        // kSegments pop counters of the front region, kHeadStride ints apart, zeroed
+  int* in_heads_long;   // the same for the back region
   int* out_queue;       // rays that finished this level (next level / hits); may be null
-  int* out_count;
+  int* out_count;       // front region of out_queue
+  int* out_count_long;  // back region (rays that took >= long_steps evaluations); null: no split
+  int long_steps;
   int n;
   int level;
   int m;

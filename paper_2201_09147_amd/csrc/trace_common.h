@@ -40,6 +40,41 @@ __device__ inline void center_at(const DevBase& B, float t, float& cx, float& cy
 #endif
 __device__ inline int queue_slot(int idx, int n) { return NNM_QUEUE_LIFO ? n - 1 - idx : idx; }
 
+// A level's output queue (an array of n ray ids) holds two regions: rays that
+// left the level in fewer than long_steps evaluations fill it from the front,
+// the others from the back.  Evaluation counts of consecutive levels are
+// strongly correlated (grazing rays are slow everywhere), so the next level
+// admits the back region first: the longest rays start first and the drain
+// tail, the latency chain of the last rays, gets shorter.  Results do not
+// depend on the order.
+__device__ inline int long_slot(int idx, int n) { return n - 1 - idx; }
+
+// One wave's ring of finished rays (2 kPushBatch entries in LDS) published
+// kPushBatch at a time with one atomic: `take` lanes (ballot `pmask` over the
+// ring's lanes, lane position `pos`) append `ray`.  from_back: the ring feeds
+// the back region of the queue.
+struct PushRing {
+  int start = 0, n = 0;
+  __device__ inline void add(int* ring, unsigned long long pmask, bool mine, int pos, int ray) {
+    if (mine) ring[(start + n + pos) & (2 * kPushBatch - 1)] = ray;
+    n += __popcll(pmask);
+  }
+  __device__ inline void publish(int* ring, int lane, int* count, int* queue, int qn, bool from_back, bool all) {
+    const int cnt = all ? n : kPushBatch;
+    __builtin_amdgcn_wave_barrier();
+    int base = 0;
+    if (lane == 0) base = atomicAdd(count, cnt);
+    base = __shfl(base, 0);
+    if (lane < cnt) {
+      const int e = ring[(start + lane) & (2 * kPushBatch - 1)];
+      queue[from_back ? long_slot(base + lane, qn) : base + lane] = e;
+    }
+    __builtin_amdgcn_wave_barrier();
+    start = (start + cnt) & (2 * kPushBatch - 1);
+    n -= cnt;
+  }
+};
+
 // Instantiates CALL(H, P) for every built (width, precision) pair.
 #define NNM_DISPATCH(WIDTH, PREC, CALL)                                   \
   switch ((WIDTH) * 4 + (PREC)) {                                         \

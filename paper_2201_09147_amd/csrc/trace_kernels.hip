@@ -39,13 +39,20 @@ k_trace_level(TraceLevelArgs A) {
   __shared__ NetSmem<H> sm;
   // Per-wave ring of rays that finished the level, flushed to the output queue
   // kPushBatch at a time (one atomic per batch, coalesced stores).
-  __shared__ int push_ring[kBlockThreads / 64][2 * kPushBatch];
+  __shared__ int push_ring[2][kBlockThreads / 64][2 * kPushBatch];
   stage_net<H>(&sm, A.L);
   const int lane = threadIdx.x & 63;
   const int col = lane & 31;
   const int g = lane >> 5;
-  int* ring = push_ring[threadIdx.x >> 6];
-  const int n_in = A.in_count ? *A.in_count : A.n;
+  int* ring = push_ring[0][threadIdx.x >> 6];
+  int* ring_l = push_ring[1][threadIdx.x >> 6];
+  // input: the back region (slow rays of the previous level) first, then the
+  // front.  Width 32 has no back region (the host splits no queue that feeds or
+  // leaves a width-32 level: at six waves per SIMD, 80 registers, the second
+  // region's state costs it more than the ordering saves).
+  const int n_long = (H != 32 && A.in_count_long) ? *A.in_count_long : 0;
+  const int n_short = A.in_count ? *A.in_count : A.n;
+  const int n_in = n_short + n_long;
   SirenTile<H, P, false> tile;
   int ray = -1, k = 0, st = 0;
   float tau = 0.f, ox = 0.f, oy = 0.f, oz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, tt = 0.f, cx = 0.f, cy = 0.f;
@@ -55,11 +62,15 @@ k_trace_level(TraceLevelArgs A) {
   // wave starts in segment (wave id mod kSegments) and moves on when it is
   // empty.  Chunks hold about n_in / (8 * resident waves) entries (32..kChunk),
   // so every wave takes several chunks and the queue drains evenly.
-  int cur = 0, end = 0, ring_start = 0, ring_n = 0;
+  int cur = 0, end = 0;
+  PushRing pr, pr_l;
   const int nwaves = gridDim.x * (kBlockThreads / 64);
   const int wave_id = blockIdx.x * (kBlockThreads / 64) + (threadIdx.x >> 6);
   const int chunk = min(kChunk, max(32, (n_in / (8 * nwaves)) & ~31));
-  const int seg_len = (n_in + kSegments - 1) / kSegments;
+  bool back = n_long > 0;  // popping the back region
+  int rn = back ? n_long : n_short;
+  int* heads = back ? A.in_heads_long : A.in_heads;
+  int seg_len = (rn + kSegments - 1) / kSegments;
   int seg = wave_id % kSegments, seg_tries = 0;
   bool exhausted = false;
   for (;;) {
@@ -70,16 +81,24 @@ k_trace_level(TraceLevelArgs A) {
     while (emask != 0u && !exhausted) {
       if (cur >= end) {
         const int s0 = seg * seg_len;
-        const int s_len = max(0, min(seg_len, n_in - s0));
+        const int s_len = max(0, min(seg_len, rn - s0));
         int base = 0;
-        if (lane == 0) base = atomicAdd(A.in_heads + seg * kHeadStride, chunk);
+        if (lane == 0) base = atomicAdd(heads + seg * kHeadStride, chunk);
         base = __shfl(base, 0);
         if (base >= s_len) {
-          // this segment is drained: try the next one
+          // this segment is drained: try the next one, then the front region
           seg = (seg + 1) % kSegments;
           if (++seg_tries >= kSegments) {
-            exhausted = true;
-            break;
+            if (!back) {
+              exhausted = true;
+              break;
+            }
+            back = false;
+            rn = n_short;
+            heads = A.in_heads;
+            seg_len = (rn + kSegments - 1) / kSegments;
+            seg = wave_id % kSegments;
+            seg_tries = 0;
           }
           continue;
         }
@@ -93,7 +112,7 @@ k_trace_level(TraceLevelArgs A) {
         const int pos = __popc(emask & ((1u << col) - 1u));
         if (pos < take) {
           const int idx = cur + pos;
-          ray = A.in_queue ? A.in_queue[queue_slot(idx, n_in)] : idx;
+          ray = A.in_queue ? A.in_queue[back ? long_slot(idx, A.n) : queue_slot(idx, rn)] : idx;
           ox = A.o[3 * ray + 0];
           oy = A.o[3 * ray + 1];
           oz = A.o[3 * ray + 2];
@@ -160,21 +179,22 @@ k_trace_level(TraceLevelArgs A) {
         }
       }
     }
-    // Compaction: rays that finished the level enter the wave's push ring.
-    const unsigned int pmask = (unsigned int)__ballot(outcome == 1);
-    if (pmask && A.out_queue) {
-      if (outcome == 1 && g == 0)
-        ring[(ring_start + ring_n + __popc(pmask & ((1u << col) - 1u))) & (2 * kPushBatch - 1)] = ray;
-      ring_n += __popc(pmask);
-      if (ring_n >= kPushBatch) {
-        __builtin_amdgcn_wave_barrier();
-        int base = 0;
-        if (lane == 0) base = atomicAdd(A.out_count, kPushBatch);
-        base = __shfl(base, 0);
-        if (lane < kPushBatch) A.out_queue[base + lane] = ring[(ring_start + lane) & (2 * kPushBatch - 1)];
-        __builtin_amdgcn_wave_barrier();
-        ring_start = (ring_start + kPushBatch) & (2 * kPushBatch - 1);
-        ring_n -= kPushBatch;
+    // Compaction: rays that finished the level enter the wave's push rings
+    // (both halves of a column hold the same slot: the lower half's ballot).
+    if (A.out_queue && __ballot(outcome == 1)) {
+      const bool slow = H != 32 && A.out_count_long && k >= A.long_steps;
+      const unsigned long long pm = (unsigned int)__ballot(outcome == 1 && !slow);
+      const unsigned long long below = (1ull << col) - 1ull;
+      if (pm) {
+        pr.add(ring, pm, outcome == 1 && !slow && g == 0, __popcll(pm & below), ray);
+        if (pr.n >= kPushBatch) pr.publish(ring, lane, A.out_count, A.out_queue, A.n, false, false);
+      }
+      if (H != 32) {
+        const unsigned long long pl = (unsigned int)__ballot(outcome == 1 && slow);
+        if (pl) {
+          pr_l.add(ring_l, pl, outcome == 1 && slow && g == 0, __popcll(pl & below), ray);
+          if (pr_l.n >= kPushBatch) pr_l.publish(ring_l, lane, A.out_count_long, A.out_queue, A.n, true, false);
+        }
       }
     }
     if (outcome != 0) {
@@ -201,14 +221,9 @@ k_trace_level(TraceLevelArgs A) {
       ray = -1;
     }
   }
-  // Flush what is left in the push ring.
-  if (ring_n > 0 && A.out_queue) {
-    __builtin_amdgcn_wave_barrier();
-    int base = 0;
-    if (lane == 0) base = atomicAdd(A.out_count, ring_n);
-    base = __shfl(base, 0);
-    if (lane < ring_n) A.out_queue[base + lane] = ring[(ring_start + lane) & (2 * kPushBatch - 1)];
-  }
+  // Flush what is left in the push rings.
+  if (pr.n > 0 && A.out_queue) pr.publish(ring, lane, A.out_count, A.out_queue, A.n, false, true);
+  if (H != 32 && pr_l.n > 0 && A.out_queue) pr_l.publish(ring_l, lane, A.out_count_long, A.out_queue, A.n, true, true);
 }
 
 // Forward + three tangent columns at the hit points (or at given points); unit

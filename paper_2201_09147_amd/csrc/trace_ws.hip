@@ -72,7 +72,7 @@ struct PipeSmem {
   int stop[2];
   int simd_count[4];
   int role_of[8];
-  int ring[2 * kPushBatch];
+  int ring[2][2 * kPushBatch];  // tracing: finished rays for the front / back region of the output queue
 };
 
 template <int P>
@@ -456,15 +456,22 @@ struct TraceCtl {
   float s_ox, s_oy, s_oz, s_vx, s_vy, s_vz, s_tt, s_tau;
   int s_head, s_count;
   int cur, end, seg, seg_tries, chunk, seg_len, n_in;
-  bool exhausted;
-  int ring_start, ring_n;
+  int n_short, n_long;  // input: back region (slow rays of the previous level, admitted first), front region
+  int* heads;
+  bool back, exhausted;
+  PushRing pr, pr_l;
   int glive;  // bit G: slot group G holds rays
   int park_head, park_count;
 
   __device__ inline void init(const TraceLevelArgs& A) {
     glive = 0;
     park_head = park_count = 0;
-    n_in = A.in_count ? *A.in_count : A.n;
+    n_long = A.in_count_long ? *A.in_count_long : 0;
+    n_short = A.in_count ? *A.in_count : A.n;
+    back = n_long > 0;
+    heads = back ? A.in_heads_long : A.in_heads;
+    const int n_all = n_short + n_long;
+    n_in = back ? n_long : n_short;
     s_ray = -1;
     s_st = 0;
     s_ox = s_oy = s_oz = s_vx = s_vy = s_vz = s_tt = s_tau = 0.f;
@@ -473,12 +480,11 @@ struct TraceCtl {
 #ifndef NNM_WS_CHUNK_DIV
 #define NNM_WS_CHUNK_DIV 8
 #endif
-    chunk = min(kChunk, max(64, (n_in / (NNM_WS_CHUNK_DIV * (int)gridDim.x)) & ~63));
+    chunk = min(kChunk, max(64, (n_all / (NNM_WS_CHUNK_DIV * (int)gridDim.x)) & ~63));
     seg_len = (n_in + kSegments - 1) / kSegments;
     seg = blockIdx.x % kSegments;
     seg_tries = 0;
     exhausted = false;
-    ring_start = ring_n = 0;
   }
 
   // Fill the staging ring up to 64 entries from the segmented input queue.
@@ -488,11 +494,23 @@ struct TraceCtl {
         const int s0 = seg * seg_len;
         const int s_len = max(0, min(seg_len, n_in - s0));
         int base = 0;
-        if (lane == 0) base = atomicAdd(A.in_heads + seg * kHeadStride, chunk);
+        if (lane == 0) base = atomicAdd(heads + seg * kHeadStride, chunk);
         base = __shfl(base, 0);
         if (base >= s_len) {
+          // this segment is drained: the next one, then the front region
           seg = (seg + 1) % kSegments;
-          if (++seg_tries >= kSegments) exhausted = true;
+          if (++seg_tries >= kSegments) {
+            if (back) {
+              back = false;
+              n_in = n_short;
+              heads = A.in_heads;
+              seg_len = (n_in + kSegments - 1) / kSegments;
+              seg = blockIdx.x % kSegments;
+              seg_tries = 0;
+            } else {
+              exhausted = true;
+            }
+          }
           continue;
         }
         cur = s0 + base;
@@ -502,7 +520,7 @@ struct TraceCtl {
       const int q = ((lane - s_head) & 63) - s_count;
       if (q >= 0 && q < add) {
         const int idx = cur + q;
-        s_ray = A.in_queue ? A.in_queue[queue_slot(idx, n_in)] : idx;
+        s_ray = A.in_queue ? A.in_queue[back ? long_slot(idx, A.n) : queue_slot(idx, n_in)] : idx;
         s_ox = A.o[3 * s_ray + 0];
         s_oy = A.o[3 * s_ray + 1];
         s_oz = A.o[3 * s_ray + 2];
@@ -525,30 +543,27 @@ struct TraceCtl {
     }
   }
 
-  __device__ inline void push(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int lane, bool hit, int ray) {
-    const unsigned long long pmask = __ballot(hit);
-    if (!pmask || !A.out_queue) return;
-    if (hit) sm.ring[(ring_start + ring_n + __popcll(pmask & ((1ull << lane) - 1ull))) & (2 * kPushBatch - 1)] = ray;
-    ring_n += __popcll(pmask);
-    if (ring_n >= kPushBatch) {
-      __builtin_amdgcn_wave_barrier();
-      int base = 0;
-      if (lane == 0) base = atomicAdd(A.out_count, kPushBatch);
-      base = __shfl(base, 0);
-      A.out_queue[base + lane] = sm.ring[(ring_start + lane) & (2 * kPushBatch - 1)];
-      __builtin_amdgcn_wave_barrier();
-      ring_start = (ring_start + kPushBatch) & (2 * kPushBatch - 1);
-      ring_n -= kPushBatch;
+  // Rays that left the level (to the next level or the normal pass): slow
+  // ones (at least long_steps evaluations here) to the back region.
+  __device__ inline void push(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int lane, bool done, int ray, int k) {
+    if (!A.out_queue || !__ballot(done)) return;
+    const bool slow = A.out_count_long && k >= A.long_steps;
+    const unsigned long long pm = __ballot(done && !slow), pl = __ballot(done && slow);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (pm) {
+      pr.add(sm.ring[0], pm, done && !slow, __popcll(pm & below), ray);
+      if (pr.n >= kPushBatch) pr.publish(sm.ring[0], lane, A.out_count, A.out_queue, A.n, false, false);
+    }
+    if (pl) {
+      pr_l.add(sm.ring[1], pl, done && slow, __popcll(pl & below), ray);
+      if (pr_l.n >= kPushBatch) pr_l.publish(sm.ring[1], lane, A.out_count_long, A.out_queue, A.n, true, false);
     }
   }
 
   __device__ inline void flush(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int lane) {
-    if (ring_n == 0 || !A.out_queue) return;
-    __builtin_amdgcn_wave_barrier();
-    int base = 0;
-    if (lane == 0) base = atomicAdd(A.out_count, ring_n);
-    base = __shfl(base, 0);
-    if (lane < ring_n) A.out_queue[base + lane] = sm.ring[(ring_start + lane) & (2 * kPushBatch - 1)];
+    if (!A.out_queue) return;
+    if (pr.n > 0) pr.publish(sm.ring[0], lane, A.out_count, A.out_queue, A.n, false, true);
+    if (pr_l.n > 0) pr_l.publish(sm.ring[1], lane, A.out_count_long, A.out_queue, A.n, true, true);
   }
 
   // Stage s (s = -1: prologue): finish tile s-4, refill its group, write tile s+1.
@@ -617,7 +632,7 @@ struct TraceCtl {
         }
       }
     }
-    push(sm, A, lane, outcome == 1, ray);
+    push(sm, A, lane, outcome == 1, ray, k);
     if (outcome != 0) {
       if (A.steps) A.steps[(long long)ray * A.m + A.level] = (uint8_t)k;
       if (outcome == 2) {
