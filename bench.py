@@ -92,6 +92,7 @@ def run_form(scene, precision, o, v, t, steps, warmup, final_level=-1, normal_le
         f"{timing['median_ms']:.3f} min {timing['min_ms']:.3f} p90 {timing['p90_ms']:.3f} ms; "
         f"stack load {load_ms:.1f} ms")
     evals = out["steps"].to(torch.int64).sum(dim=0).cpu().tolist()
+    entering = (out["steps"] > 0).to(torch.int64).sum(dim=0).cpu().tolist()
     hits = int(out["hit"].to(torch.int64).sum().item())
     kernels = []
     for e in report:
@@ -99,6 +100,9 @@ def run_form(scene, precision, o, v, t, steps, warmup, final_level=-1, normal_le
         if e["kind"] == "trace":
             flops = evals[e["level"]] * hidden_flops(lvl.net)
             units = evals[e["level"]]
+        elif e["kind"] == "order":  # queue entries sorted for the next level
+            flops = 0
+            units = entering[e["level"] + 1]
         else:
             flops = hits * normal_hidden_flops(lvl.net)
             units = hits

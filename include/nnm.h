@@ -180,8 +180,8 @@ int trace_rays(const nnm_stack* stack, const nnm_trace_params* params, int64_t n
 /* trace_rays for callers that cannot allocate: code under HIP graph capture,
    tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
    kernels and results as trace_rays, but it calls no hipMalloc, hipFree or
-   allocating routine: its scratch (ray queues, counters, status carrier;
-   about 19 MB) is a static device array of the library, one per GPU, which
+   allocating routine: its scratch (ray queues, order keys, counters, status carrier;
+   about 21 MB) is a static device array of the library, one per GPU, which
    each GPU the library runs on holds until the process ends.  Its address is
    looked up on the first call on a device.
    Every call on one GPU uses that GPU's one array: calls that may overlap in
@@ -427,9 +427,11 @@ int nnm_mesh_extract(const float* values, int32_t res, float lo, float hi, float
 /* A profiler records a HIP event pair around every kernel that trace_rays
    launches while it is attached to the trace parameters (events on the call's
    stream; no synchronisation until a report is requested).  Entries are keyed
-   by (kind, level, variant): kind 0 = tracing of one level, 1 = normal pass;
-   variant 0 = single-wave streaming tile (k_trace_level / k_normal),
-   1 = pipelined weight-stationary workgroup (k_trace_ws / k_normal_ws). */
+   by (kind, level, variant): kind 0 = tracing of one level, 1 = normal pass,
+   2 = ordering of level `level`'s output queue for the next level
+   (k_queue_order, variant 0); variant 0 = single-wave streaming tile
+   (k_trace_level / k_normal), 1 = pipelined weight-stationary workgroup
+   (k_trace_ws / k_normal_ws). */
 #define NNM_PROF_MAX 32
 typedef struct {
   int32_t n_entries;

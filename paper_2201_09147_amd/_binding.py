@@ -269,14 +269,15 @@ class Profiler:
         _check(load_library().nnm_profiler_reset(self._h))
 
     def report(self):
-        """List of dicts (kind 'trace'/'normal', level, width, kernel, variant, launches, total_ms)."""
+        """List of dicts (kind 'trace'/'normal'/'order', level, width, kernel, variant, launches,
+        total_ms); 'order' is the sort of level `level`'s output queue."""
         r = _ProfileReport()
         _check(load_library().nnm_profiler_report(self._h, ctypes.cast(ctypes.byref(r), c_void_p)))
         names = {("trace", 0): "k_trace_level", ("trace", 1): "k_trace_ws",
-                 ("normal", 0): "k_normal", ("normal", 1): "k_normal_ws"}
+                 ("normal", 0): "k_normal", ("normal", 1): "k_normal_ws", ("order", 0): "k_queue_order"}
         out = []
         for i in range(r.n_entries):
-            kind = ("trace", "normal")[r.kind[i]]
+            kind = ("trace", "normal", "order")[r.kind[i]]
             out.append({"kind": kind, "level": r.level[i], "width": r.width[i],
                         "kernel": names[(kind, r.variant[i])], "variant": int(r.variant[i]),
                         "launches": int(r.launches[i]), "total_ms": float(r.total_ms[i])})

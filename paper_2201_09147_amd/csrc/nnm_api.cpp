@@ -504,18 +504,21 @@ static bool level_reads_time(const nnm_stack* s, int j) {
 int nnm_stack_levels(const nnm_stack* s) { return s ? s->m : -1; }
 int nnm_stack_precision(const nnm_stack* s) { return s ? s->precision : -1; }
 
-// Scratch of one trace_rays call: counters (head and out count per level), two
-// ping-pong queues, and the status carrier when the caller passes none.
-// cnt[2j], cnt[2j+1]: rays out of level j in the back / front region of its
-// output queue; the pop heads of level j's input at cnt + 64 + (2j + r) *
-// kSegments * kHeadStride (r = 0 back, 1 front region).
+// Scratch of one trace_rays call: counters, two ping-pong queues, the order
+// keys of the queue being written (by queue position), and the status carrier
+// when the caller passes none.
 struct TraceScratch {
-  static constexpr int n_cnt = 64 + 2 * kMaxLevels * kSegments * kHeadStride;
-  size_t off_qa, off_qb, off_st, total;
-  constexpr TraceScratch(int64_t n, bool status) : off_qa(0), off_qb(0), off_st(0), total(0) {
+  // counters: [0, 64) queue counts per level; then per level kOrderKeys key
+  // totals and kOrderKeys reservation counters; then per level kSegments pop
+  // counters kHeadStride ints apart
+  static constexpr int n_fixed = 64 + kMaxLevels * 2 * kOrderKeys;
+  static constexpr int n_cnt = n_fixed + kMaxLevels * kSegments * kHeadStride;
+  size_t off_qa, off_qb, off_key, off_st, total;
+  constexpr TraceScratch(int64_t n, bool status) : off_qa(0), off_qb(0), off_key(0), off_st(0), total(0) {
     off_qa = align256((size_t)n_cnt * 4);
     off_qb = off_qa + align256((size_t)n * 4);
-    off_st = off_qb + align256((size_t)n * 4);
+    off_key = off_qb + align256((size_t)n * 4);
+    off_st = off_key + align256((size_t)n);
     total = off_st + (status ? 0 : align256((size_t)n));
   }
 };
@@ -560,14 +563,25 @@ static int trace_launch(const nnm_stack* s, const nnm_trace_params* p, int64_t n
   const TraceScratch sc(n, status != nullptr);
   const int L = p->final_level + 1;
   int* cnt = (int*)wb;
-  int* q[2] = {(int*)(wb + sc.off_qa), (int*)(wb + sc.off_qb)};
+  int* qa = (int*)(wb + sc.off_qa);
+  int* qb = (int*)(wb + sc.off_qb);
+  uint8_t* key = (uint8_t*)(wb + sc.off_key);
   uint8_t* stat = status ? status : (uint8_t*)(wb + sc.off_st);
   int rc = NNM_OK;
   hipError_t e;
-  if ((e = launch_zero_ints(cnt, 64 + 2 * L * kSegments * kHeadStride, st)) != hipSuccess)
+  if ((e = launch_zero_ints(cnt, TraceScratch::n_fixed + L * kSegments * kHeadStride, st)) != hipSuccess)
     rc = hip_fail(e, "zeroing counters");
+  // Level j pops in_q and appends to out_q.  Between tracing levels (mode 0)
+  // the appended queue is counting-sorted by decreasing evaluation count into
+  // the other buffer, which the next level pops; otherwise the buffers swap.
+  const int* in_q = nullptr;
+  int* out_q = qa;
+  int* spare = qb;
   for (int j = 0; j < L && rc == NNM_OK; ++j) {
     const auto& lv = s->levels[j];
+    const bool is_final = (j == L - 1);
+    const bool sort_next = !is_final && p->mode == 0;
+    int* hist = cnt + 64 + j * 2 * kOrderKeys;
     TraceLevelArgs a{};
     a.L = lv.dev;
     a.B = s->base;
@@ -579,22 +593,13 @@ static int trace_launch(const nnm_stack* s, const nnm_trace_params* p, int64_t n
     a.normal = normal;
     a.steps = steps;
     a.status = stat;
-    a.in_queue = j == 0 ? nullptr : q[(j - 1) & 1];
-    a.in_count = j == 0 ? nullptr : cnt + 2 * (j - 1) + 1;
-    a.in_count_long = j == 0 ? nullptr : cnt + 2 * (j - 1);
-    a.in_heads = cnt + 64 + (2 * j + 1) * kSegments * kHeadStride;
-    a.in_heads_long = cnt + 64 + 2 * j * kSegments * kHeadStride;
-    const bool is_final = (j == L - 1);
-    a.out_queue = (!is_final || normal) ? q[j & 1] : nullptr;
-    a.out_count = cnt + 2 * j + 1;
-    // slow rays go to the back region of the next level's queue (not for the
-    // normal pass, which has no iterations, nor in fixed-iteration mode, where
-    // every ray takes the same count, nor to or from a width-32 level, whose
-    // kernel keeps one region)
-    a.out_count_long = (!is_final && p->mode == 0 && lv.width != 32 && s->levels[j + 1].width != 32)
-                           ? cnt + 2 * j
-                           : nullptr;
-    a.long_steps = kLongSteps;
+    a.in_queue = in_q;
+    a.in_count = j == 0 ? nullptr : cnt + (j - 1);
+    a.in_heads = cnt + TraceScratch::n_fixed + j * kSegments * kHeadStride;
+    a.out_queue = (!is_final || normal) ? out_q : nullptr;
+    a.out_count = cnt + j;
+    a.out_key = sort_next ? key : nullptr;
+    a.out_hist = sort_next ? hist : nullptr;
     a.n = (int)n;
     a.level = j;
     a.m = s->m;
@@ -606,15 +611,34 @@ static int trace_launch(const nnm_stack* s, const nnm_trace_params* p, int64_t n
     a.fixed_iters = p->mode == 1 ? p->iterations[j] : 0;
     a.delta = is_final ? 0.f : lv.delta;
     const bool ws_kernel = lv.dev.ws_ah && p->kernels == NNM_KERNELS_AUTO;
-    ProfScope prof(p->profiler, 0, j, lv.width, ws_kernel ? 1 : 0, st);
-    if (ws_kernel) {
-      const long long want = ((long long)n + kWsRaysPerBlock - 1) / kWsRaysPerBlock;
-      const int grid = (int)std::max(1LL, std::min(want, (long long)lv.ws_resident[0]));
-      if ((e = launch_trace_ws(s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "trace level (ws)");
+    {
+      ProfScope prof(p->profiler, 0, j, lv.width, ws_kernel ? 1 : 0, st);
+      if (ws_kernel) {
+        const long long want = ((long long)n + kWsRaysPerBlock - 1) / kWsRaysPerBlock;
+        const int grid = (int)std::max(1LL, std::min(want, (long long)lv.ws_resident[0]));
+        if ((e = launch_trace_ws(s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "trace level (ws)");
+      } else {
+        const long long want = ((long long)n + 127) / 128;
+        const int grid = (int)std::max(1LL, std::min(want, (long long)lv.resident[0]));
+        if ((e = launch_trace_level(lv.width, s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "trace level");
+      }
+    }
+    if (rc != NNM_OK || is_final) break;
+    if (sort_next) {
+      QueueOrderArgs qo{};
+      qo.in = out_q;
+      qo.count = cnt + j;
+      qo.key = key;
+      qo.hist = hist;
+      qo.fill = hist + kOrderKeys;
+      qo.out = spare;
+      const int grid = (int)std::max(1LL, std::min(256LL, ((long long)n + 4095) / 4096));
+      ProfScope prof(p->profiler, 2, j, 0, 0, st);
+      if ((e = launch_queue_order(qo, grid, st)) != hipSuccess) rc = hip_fail(e, "queue order");
+      in_q = spare;  // out_q is free again
     } else {
-      const long long want = ((long long)n + 127) / 128;
-      const int grid = (int)std::max(1LL, std::min(want, (long long)lv.resident[0]));
-      if ((e = launch_trace_level(lv.width, s->precision, a, grid, st)) != hipSuccess) rc = hip_fail(e, "trace level");
+      in_q = out_q;
+      std::swap(out_q, spare);
     }
   }
   if (rc == NNM_OK && normal) {
@@ -627,8 +651,8 @@ static int trace_launch(const nnm_stack* s, const nnm_trace_params* p, int64_t n
     a.t = t;
     a.depth = depth;
     a.normal = normal;
-    a.queue = q[(L - 1) & 1];
-    a.count = cnt + 2 * (L - 1) + 1;
+    a.queue = out_q;
+    a.count = cnt + (L - 1);
     a.n = (int)n;
     const bool ws_kernel = nl.dev.ws_ah && p->kernels == NNM_KERNELS_AUTO;
     ProfScope prof(p->profiler, 1, p->normal_level, nl.width, ws_kernel ? 1 : 0, st);

@@ -31,12 +31,10 @@ constexpr int kChunk = 256;         // most queue entries a wave takes per atomi
 constexpr int kPushBatch = 64;      // queue entries a wave publishes per atomic
 constexpr int kSegments = 64;       // input queue segments, each with its own head
 constexpr int kHeadStride = 32;     // ints between segment heads (one 128-byte line each)
-#ifndef NNM_LONG_STEPS
-#define NNM_LONG_STEPS 16
-#endif
-// Rays that took at least this many evaluations at a level are admitted first
-// at the next one (the evaluation counts of consecutive levels correlate).
-constexpr int kLongSteps = NNM_LONG_STEPS;
+// Order keys of a level's output queue: min(evaluations at the level, 63).
+// The next level admits rays in decreasing key order (the evaluation counts of
+// consecutive levels correlate, so its longest rays start first).
+constexpr int kOrderKeys = 64;
 constexpr int kPipeGroups = 5;       // slot groups in flight in a weight-stationary workgroup
 #ifndef NNM_WS_TRACE_COLS
 #define NNM_WS_TRACE_COLS 32           // columns (rays) of a weight-stationary tracing tile

@@ -23,14 +23,12 @@ struct TraceLevelArgs {
   uint8_t* steps;       // [n][m], may be null
   uint8_t* status;      // never null (library scratch when the caller passes null)
   const int* in_queue;  // null: ray ids 0..n-1
-  const int* in_count;  // entries in the front region of in_queue; null: n
-  const int* in_count_long;  // entries in the back region (admitted first); null: none
-  int* in_heads;        // kSegments pop counters of the front region, kHeadStride ints apart, zeroed
-  int* in_heads_long;   // the same for the back region
+  const int* in_count;  // entries of in_queue; null: n
+  int* in_heads;        // kSegments pop counters, kHeadStride ints apart, zeroed
   int* out_queue;       // rays that finished this level (next level / hits); may be null
-  int* out_count;       // front region of out_queue
-  int* out_count_long;  // back region (rays that took >= long_steps evaluations); null: no split
-  int long_steps;
+  int* out_count;       // entries appended to out_queue
+  uint8_t* out_key;     // [n] order key of each out_queue entry (same position); null: none
+  int* out_hist;        // [kOrderKeys] entries pushed per key, zeroed; with out_key
   int n;
   int level;
   int m;
@@ -41,6 +39,19 @@ struct TraceLevelArgs {
   float far;
   float delta;  // delta of this level; 0 on the final level
   int fixed_iters;  // > 0: fixed-iteration mode, exactly this many steps at this level
+};
+
+// Reorders a level's output queue by decreasing order key (a counting sort on
+// the per-key totals the level accumulated) into the segment layout the next
+// level pops: runs of consecutive ranks dealt round-robin to the segments, so
+// every segment holds its share of the longest rays at its front.
+struct QueueOrderArgs {
+  const int* in;        // unsorted queue
+  const int* count;     // its entries (device)
+  const uint8_t* key;   // order key of each entry of `in`
+  const int* hist;      // [kOrderKeys] entries per key
+  int* fill;            // [kOrderKeys] reservation counters, zeroed
+  int* out;             // sorted queue (same count)
 };
 
 // Analytic normal of one level at the end points of the rays in a queue.
@@ -183,6 +194,7 @@ hipError_t launch_box_points(uint64_t seed, long long base, int count, float lo,
 hipError_t launch_ref_sdf(const float* x, int count, int kind, float a, float b, float* out, hipStream_t s);
 hipError_t launch_absdiff_max(const float* fa, const float* fb, int count, unsigned int* out, hipStream_t s);
 hipError_t launch_trace_level(int width, int prec, const TraceLevelArgs& a, int grid, hipStream_t s);
+hipError_t launch_queue_order(const QueueOrderArgs& a, int grid, hipStream_t s);
 hipError_t launch_normal(int width, int prec, const NormalArgs& a, int grid, hipStream_t s);
 hipError_t launch_points(int width, int prec, const PointsArgs& a, int grid, hipStream_t s);
 hipError_t launch_trace_ws(int prec, const TraceLevelArgs& a, int grid, hipStream_t s);

@@ -30,44 +30,64 @@ __device__ inline void center_at(const DevBase& B, float t, float& cx, float& cy
   }
 }
 
-// Position of the idx-th popped entry of a level's input queue of n entries.
-// The previous level appends rays in the order they finish, so the slowest
-// rays of that level (grazing ones, which are also slow at this level) sit at
-// the end; reading the queue backwards admits them first and shortens the
-// drain tail.  Results do not depend on the order.
-#ifndef NNM_QUEUE_LIFO
-#define NNM_QUEUE_LIFO 1
-#endif
-__device__ inline int queue_slot(int idx, int n) { return NNM_QUEUE_LIFO ? n - 1 - idx : idx; }
+// A level's input queue is popped from kSegments segments at once.  Sorted
+// input is laid out in runs of kOrderRun consecutive ranks dealt round-robin
+// to the segments (run c to segment c mod kSegments), so every segment starts
+// with its share of the longest rays and a run of neighbouring queue entries
+// stays together.  segment_bounds gives segment `seg`'s entries [start,
+// start + len) of a queue of n; the last run (n mod kOrderRun entries, if
+// not zero) is the short one.
+constexpr int kOrderRun = 64;
+__device__ inline void segment_bounds(int seg, int n, int& start, int& len) {
+  const int runs = (n + kOrderRun - 1) / kOrderRun;
+  const int full = runs / kSegments, extra = runs - full * kSegments;
+  const int last_seg = runs > 0 ? (runs - 1) % kSegments : -1;
+  const int short_by = runs * kOrderRun - n;
+  start = (seg * full + min(seg, extra)) * kOrderRun - (seg > last_seg ? short_by : 0);
+  len = (full + (seg < extra ? 1 : 0)) * kOrderRun - (seg == last_seg ? short_by : 0);
+}
 
-// A level's output queue (an array of n ray ids) holds two regions: rays that
-// left the level in fewer than long_steps evaluations fill it from the front,
-// the others from the back.  Evaluation counts of consecutive levels are
-// strongly correlated (grazing rays are slow everywhere), so the next level
-// admits the back region first: the longest rays start first and the drain
-// tail, the latency chain of the last rays, gets shorter.  Results do not
-// depend on the order.
-__device__ inline int long_slot(int idx, int n) { return n - 1 - idx; }
+// Queue position of sorted rank r in that layout.
+__device__ inline int sorted_position(int r, int n) {
+  const int c = r / kOrderRun;
+  int start, len;
+  segment_bounds(c % kSegments, n, start, len);
+  return start + (c / kSegments) * kOrderRun + (r - c * kOrderRun);
+}
 
-// One wave's ring of finished rays (2 kPushBatch entries in LDS) published
-// kPushBatch at a time with one atomic: `take` lanes (ballot `pmask` over the
-// ring's lanes, lane position `pos`) append `ray`.  from_back: the ring feeds
-// the back region of the queue.
+__device__ inline int order_key(int k) { return min(k, kOrderKeys - 1); }
+
+// One wave's ring of finished rays and their order keys (2 kPushBatch entries
+// each in LDS) published kPushBatch at a time with one atomic: the lanes of
+// ballot `pmask` (the ring's lanes; this lane's position `pos`) append `ray`.
+// With keys (queue_key non-null) publishing also stores each entry's key at
+// its queue position and counts it in the LDS histogram `hist`.
 struct PushRing {
   int start = 0, n = 0;
-  __device__ inline void add(int* ring, unsigned long long pmask, bool mine, int pos, int ray) {
-    if (mine) ring[(start + n + pos) & (2 * kPushBatch - 1)] = ray;
+  __device__ inline void add(int* ring, uint8_t* ring_key, unsigned long long pmask, bool mine, int pos, int ray,
+                             int key) {
+    if (mine) {
+      const int e = (start + n + pos) & (2 * kPushBatch - 1);
+      ring[e] = ray;
+      if (ring_key) ring_key[e] = (uint8_t)key;
+    }
     n += __popcll(pmask);
   }
-  __device__ inline void publish(int* ring, int lane, int* count, int* queue, int qn, bool from_back, bool all) {
+  __device__ inline void publish(int* ring, const uint8_t* ring_key, int lane, int* count, int* queue,
+                                 uint8_t* queue_key, int* hist, bool all) {
     const int cnt = all ? n : kPushBatch;
     __builtin_amdgcn_wave_barrier();
     int base = 0;
     if (lane == 0) base = atomicAdd(count, cnt);
     base = __shfl(base, 0);
     if (lane < cnt) {
-      const int e = ring[(start + lane) & (2 * kPushBatch - 1)];
-      queue[from_back ? long_slot(base + lane, qn) : base + lane] = e;
+      const int e = (start + lane) & (2 * kPushBatch - 1);
+      queue[base + lane] = ring[e];
+      if (queue_key) {
+        const int key = ring_key[e];
+        queue_key[base + lane] = (uint8_t)key;
+        atomicAdd(hist + key, 1);
+      }
     }
     __builtin_amdgcn_wave_barrier();
     start = (start + cnt) & (2 * kPushBatch - 1);

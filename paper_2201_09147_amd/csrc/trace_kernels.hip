@@ -22,10 +22,11 @@ __global__ void k_zero_ints(int* p, int count) {
 
 // Waves per SIMD the tracing kernel of width H is compiled for (the register
 // budget follows: 512 / waves per lane, VGPRs and accumulator registers together).
-// Width 32 runs 4% faster at 6 waves (a few spilled registers on the refill
-// path) than at its natural 5; width 64 gains nothing from 4 and loses at 5.
+// Width 32 runs at its natural 5 (96 registers, no spills; at 6 waves, 80
+// registers, it spills on the refill and push paths and runs 4% slower);
+// width 64 gains nothing from 4 and loses at 5.
 #ifndef NNM_TRACE_WAVES_32
-#define NNM_TRACE_WAVES_32 6
+#define NNM_TRACE_WAVES_32 5
 #endif
 #ifndef NNM_TRACE_WAVES_64
 #define NNM_TRACE_WAVES_64 1
@@ -38,67 +39,53 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
 k_trace_level(TraceLevelArgs A) {
   __shared__ NetSmem<H> sm;
   // Per-wave ring of rays that finished the level, flushed to the output queue
-  // kPushBatch at a time (one atomic per batch, coalesced stores).
-  __shared__ int push_ring[2][kBlockThreads / 64][2 * kPushBatch];
-  stage_net<H>(&sm, A.L);
+  // kPushBatch at a time (one atomic per batch, coalesced stores), and the
+  // workgroup's count of pushed rays per order key.
+  __shared__ int push_ring[kBlockThreads / 64][2 * kPushBatch];
+  __shared__ uint8_t push_key[kBlockThreads / 64][2 * kPushBatch];
+  __shared__ int key_hist[kOrderKeys];
+  if (threadIdx.x < kOrderKeys) key_hist[threadIdx.x] = 0;
+  stage_net<H>(&sm, A.L);  // (ends with a workgroup barrier)
   const int lane = threadIdx.x & 63;
   const int col = lane & 31;
   const int g = lane >> 5;
-  int* ring = push_ring[0][threadIdx.x >> 6];
-  int* ring_l = push_ring[1][threadIdx.x >> 6];
-  // input: the back region (slow rays of the previous level) first, then the
-  // front.  Width 32 has no back region (the host splits no queue that feeds or
-  // leaves a width-32 level: at six waves per SIMD, 80 registers, the second
-  // region's state costs it more than the ordering saves).
-  const int n_long = (H != 32 && A.in_count_long) ? *A.in_count_long : 0;
-  const int n_short = A.in_count ? *A.in_count : A.n;
-  const int n_in = n_short + n_long;
+  int* ring = push_ring[threadIdx.x >> 6];
+  uint8_t* ring_key = A.out_key ? push_key[threadIdx.x >> 6] : nullptr;
+  const int n_in = A.in_count ? *A.in_count : A.n;
   SirenTile<H, P, false> tile;
   int ray = -1, k = 0, st = 0;
   float tau = 0.f, ox = 0.f, oy = 0.f, oz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, tt = 0.f, cx = 0.f, cy = 0.f;
   // Wave-uniform work chunk [cur, end) of the input queue and push-ring state.
-  // The queue is split into kSegments contiguous segments with one pop counter
-  // each (separate cache lines, so the atomics spread over many addresses); a
-  // wave starts in segment (wave id mod kSegments) and moves on when it is
-  // empty.  Chunks hold about n_in / (8 * resident waves) entries (32..kChunk),
-  // so every wave takes several chunks and the queue drains evenly.
+  // The queue is split into kSegments segments with one pop counter each
+  // (separate cache lines, so the atomics spread over many addresses); a wave
+  // starts in segment (wave id mod kSegments) and moves on when it is empty.
+  // Chunks hold about n_in / (8 * resident waves) entries (32..kChunk), so
+  // every wave takes several chunks and the queue drains evenly.
   int cur = 0, end = 0;
-  PushRing pr, pr_l;
+  PushRing pr;
   const int nwaves = gridDim.x * (kBlockThreads / 64);
   const int wave_id = blockIdx.x * (kBlockThreads / 64) + (threadIdx.x >> 6);
   const int chunk = min(kChunk, max(32, (n_in / (8 * nwaves)) & ~31));
-  bool back = n_long > 0;  // popping the back region
-  int rn = back ? n_long : n_short;
-  int* heads = back ? A.in_heads_long : A.in_heads;
-  int seg_len = (rn + kSegments - 1) / kSegments;
   int seg = wave_id % kSegments, seg_tries = 0;
   bool exhausted = false;
   for (;;) {
     // Refill empty slots from the wave's chunk, grabbing a new chunk of
-    // kChunk queue entries (one atomic) when it runs dry.  Both halves of a
-    // column hold the same slot state, so the lower half's ballot is enough.
+    // queue entries (one atomic) when it runs dry.  Both halves of a column
+    // hold the same slot state, so the lower half's ballot is enough.
     unsigned int emask = (unsigned int)__ballot(ray < 0);
     while (emask != 0u && !exhausted) {
       if (cur >= end) {
-        const int s0 = seg * seg_len;
-        const int s_len = max(0, min(seg_len, rn - s0));
+        int s0, s_len;
+        segment_bounds(seg, n_in, s0, s_len);
         int base = 0;
-        if (lane == 0) base = atomicAdd(heads + seg * kHeadStride, chunk);
+        if (lane == 0) base = atomicAdd(A.in_heads + seg * kHeadStride, chunk);
         base = __shfl(base, 0);
         if (base >= s_len) {
-          // this segment is drained: try the next one, then the front region
+          // this segment is drained: try the next one
           seg = (seg + 1) % kSegments;
           if (++seg_tries >= kSegments) {
-            if (!back) {
-              exhausted = true;
-              break;
-            }
-            back = false;
-            rn = n_short;
-            heads = A.in_heads;
-            seg_len = (rn + kSegments - 1) / kSegments;
-            seg = wave_id % kSegments;
-            seg_tries = 0;
+            exhausted = true;
+            break;
           }
           continue;
         }
@@ -112,7 +99,7 @@ k_trace_level(TraceLevelArgs A) {
         const int pos = __popc(emask & ((1u << col) - 1u));
         if (pos < take) {
           const int idx = cur + pos;
-          ray = A.in_queue ? A.in_queue[back ? long_slot(idx, A.n) : queue_slot(idx, rn)] : idx;
+          ray = A.in_queue ? A.in_queue[idx] : idx;
           ox = A.o[3 * ray + 0];
           oy = A.o[3 * ray + 1];
           oz = A.o[3 * ray + 2];
@@ -179,22 +166,13 @@ k_trace_level(TraceLevelArgs A) {
         }
       }
     }
-    // Compaction: rays that finished the level enter the wave's push rings
+    // Compaction: rays that finished the level enter the wave's push ring
     // (both halves of a column hold the same slot: the lower half's ballot).
-    if (A.out_queue && __ballot(outcome == 1)) {
-      const bool slow = H != 32 && A.out_count_long && k >= A.long_steps;
-      const unsigned long long pm = (unsigned int)__ballot(outcome == 1 && !slow);
-      const unsigned long long below = (1ull << col) - 1ull;
+    if (A.out_queue) {
+      const unsigned long long pm = (unsigned int)__ballot(outcome == 1);
       if (pm) {
-        pr.add(ring, pm, outcome == 1 && !slow && g == 0, __popcll(pm & below), ray);
-        if (pr.n >= kPushBatch) pr.publish(ring, lane, A.out_count, A.out_queue, A.n, false, false);
-      }
-      if (H != 32) {
-        const unsigned long long pl = (unsigned int)__ballot(outcome == 1 && slow);
-        if (pl) {
-          pr_l.add(ring_l, pl, outcome == 1 && slow && g == 0, __popcll(pl & below), ray);
-          if (pr_l.n >= kPushBatch) pr_l.publish(ring_l, lane, A.out_count_long, A.out_queue, A.n, true, false);
-        }
+        pr.add(ring, ring_key, pm, outcome == 1 && g == 0, __popcll(pm & ((1ull << col) - 1ull)), ray, order_key(k));
+        if (pr.n >= kPushBatch) pr.publish(ring, ring_key, lane, A.out_count, A.out_queue, A.out_key, key_hist, false);
       }
     }
     if (outcome != 0) {
@@ -221,9 +199,74 @@ k_trace_level(TraceLevelArgs A) {
       ray = -1;
     }
   }
-  // Flush what is left in the push rings.
-  if (pr.n > 0 && A.out_queue) pr.publish(ring, lane, A.out_count, A.out_queue, A.n, false, true);
-  if (H != 32 && pr_l.n > 0 && A.out_queue) pr_l.publish(ring_l, lane, A.out_count_long, A.out_queue, A.n, true, true);
+  // Flush what is left in the push ring, then the workgroup's key counts.
+  if (pr.n > 0 && A.out_queue) pr.publish(ring, ring_key, lane, A.out_count, A.out_queue, A.out_key, key_hist, true);
+  if (A.out_key) {
+    __syncthreads();
+    if (threadIdx.x < kOrderKeys) {
+      const int c = key_hist[threadIdx.x];
+      if (c) atomicAdd(A.out_hist + threadIdx.x, c);
+    }
+  }
+}
+
+// Counting sort of a level's output queue by decreasing order key (the layout
+// of QueueOrderArgs).  Workgroup b owns entries [b per, (b + 1) per) and takes
+// them kOrderBatch at a time, held in registers: it counts their keys in LDS,
+// reserves room in every key's run with one atomic per key, then scatters.
+// The order inside a key's run is unspecified (results do not depend on the
+// order rays are traced in).
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderPerThread = 4;
+constexpr int kOrderBatch = kOrderThreads * kOrderPerThread;
+__global__ void __launch_bounds__(kOrderThreads) k_queue_order(QueueOrderArgs A) {
+  __shared__ int cnt[kOrderKeys], first[kOrderKeys];
+  const int t = threadIdx.x;
+  // entries of all larger keys come first: a suffix sum over the key totals
+  int larger = 0;
+  if (t < kOrderKeys) {
+    const int h = A.hist[t];
+    int s = h;
+    for (int d = 1; d < kOrderKeys; d <<= 1) {
+      const int o = __shfl_down(s, d);
+      if (t + d < kOrderKeys) s += o;
+    }
+    larger = s - h;
+  }
+  const int n = *A.count;
+  const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int lo = blockIdx.x * per, hi = min(n, lo + per);
+  for (int b0 = lo; b0 < hi; b0 += kOrderBatch) {  // (uniform over the workgroup)
+    if (t < kOrderKeys) cnt[t] = 0;
+    __syncthreads();
+    int key[kOrderPerThread], ray[kOrderPerThread];
+#pragma unroll
+    for (int e = 0; e < kOrderPerThread; ++e) {
+      const int i = b0 + t + e * kOrderThreads;
+      key[e] = -1;
+      if (i < hi) {
+        key[e] = A.key[i];
+        ray[e] = A.in[i];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kOrderPerThread; ++e)
+      if (key[e] >= 0) atomicAdd(&cnt[key[e]], 1);
+    __syncthreads();
+    if (t < kOrderKeys) {
+      const int c = cnt[t];
+      first[t] = larger + (c ? atomicAdd(A.fill + t, c) : 0);
+      cnt[t] = 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kOrderPerThread; ++e) {
+      if (key[e] < 0) continue;
+      const int r = first[key[e]] + atomicAdd(&cnt[key[e]], 1);
+      if (r < n) A.out[sorted_position(r, n)] = ray[e];
+    }
+    __syncthreads();  // cnt and first are rewritten by the next batch
+  }
 }
 
 // Forward + three tangent columns at the hit points (or at given points); unit
@@ -346,6 +389,11 @@ __global__ void __launch_bounds__(kBlockThreads) k_points(PointsArgs A) {
 
 hipError_t launch_zero_ints(int* p, int count, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_ints, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_queue_order(const QueueOrderArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_queue_order, dim3(grid), dim3(kOrderThreads), 0, s, a);
   return hipGetLastError();
 }
 

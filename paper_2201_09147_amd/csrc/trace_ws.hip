@@ -50,6 +50,7 @@ constexpr int kParkMax = kTraceCols / 2;  // most survivors a group parks (tail 
 // tracing: the wave that computes role 0's first-layer block
 constexpr int kOff0Wave = (kTraceCols == 32 && NNM_WS_CTL_NOH1) ? 3 : 1;
 static_assert(kPipeGroups == 5, "tile t uses group t % 5: five tiles are in flight");
+static_assert(kOrderKeys == 64, "the control wave keeps one order key per lane");
 static_assert(kPipeGroups * kTraceCols == kWsRaysPerBlock && kPipeGroups * kNormalCols / 4 == kWsPointsPerBlock, "slots");
 
 template <int C>
@@ -72,7 +73,9 @@ struct PipeSmem {
   int stop[2];
   int simd_count[4];
   int role_of[8];
-  int ring[2][2 * kPushBatch];  // tracing: finished rays for the front / back region of the output queue
+  int ring[2 * kPushBatch];          // tracing: finished rays waiting for the output queue
+  uint8_t ring_key[2 * kPushBatch];  // tracing: their order keys
+  int hist[kOrderKeys];              // tracing: pushed rays per order key
 };
 
 template <int P>
@@ -455,23 +458,16 @@ struct TraceCtl {
   int s_ray, s_st;
   float s_ox, s_oy, s_oz, s_vx, s_vy, s_vz, s_tt, s_tau;
   int s_head, s_count;
-  int cur, end, seg, seg_tries, chunk, seg_len, n_in;
-  int n_short, n_long;  // input: back region (slow rays of the previous level, admitted first), front region
-  int* heads;
-  bool back, exhausted;
-  PushRing pr, pr_l;
+  int cur, end, seg, seg_tries, chunk, n_in;
+  bool exhausted;
+  PushRing pr;
   int glive;  // bit G: slot group G holds rays
   int park_head, park_count;
 
-  __device__ inline void init(const TraceLevelArgs& A) {
+  __device__ inline void init(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int lane) {
     glive = 0;
     park_head = park_count = 0;
-    n_long = A.in_count_long ? *A.in_count_long : 0;
-    n_short = A.in_count ? *A.in_count : A.n;
-    back = n_long > 0;
-    heads = back ? A.in_heads_long : A.in_heads;
-    const int n_all = n_short + n_long;
-    n_in = back ? n_long : n_short;
+    n_in = A.in_count ? *A.in_count : A.n;
     s_ray = -1;
     s_st = 0;
     s_ox = s_oy = s_oz = s_vx = s_vy = s_vz = s_tt = s_tau = 0.f;
@@ -480,37 +476,26 @@ struct TraceCtl {
 #ifndef NNM_WS_CHUNK_DIV
 #define NNM_WS_CHUNK_DIV 8
 #endif
-    chunk = min(kChunk, max(64, (n_all / (NNM_WS_CHUNK_DIV * (int)gridDim.x)) & ~63));
-    seg_len = (n_in + kSegments - 1) / kSegments;
+    chunk = min(kChunk, max(64, (n_in / (NNM_WS_CHUNK_DIV * (int)gridDim.x)) & ~63));
     seg = blockIdx.x % kSegments;
     seg_tries = 0;
     exhausted = false;
+    sm.hist[lane] = 0;  // (only this wave touches it)
   }
 
   // Fill the staging ring up to 64 entries from the segmented input queue.
   __device__ inline void top_up(const TraceLevelArgs& A, int lane) {
     while (s_count < 64 && !exhausted) {
       if (cur >= end) {
-        const int s0 = seg * seg_len;
-        const int s_len = max(0, min(seg_len, n_in - s0));
+        int s0, s_len;
+        segment_bounds(seg, n_in, s0, s_len);
         int base = 0;
-        if (lane == 0) base = atomicAdd(heads + seg * kHeadStride, chunk);
+        if (lane == 0) base = atomicAdd(A.in_heads + seg * kHeadStride, chunk);
         base = __shfl(base, 0);
         if (base >= s_len) {
-          // this segment is drained: the next one, then the front region
+          // this segment is drained: the next one
           seg = (seg + 1) % kSegments;
-          if (++seg_tries >= kSegments) {
-            if (back) {
-              back = false;
-              n_in = n_short;
-              heads = A.in_heads;
-              seg_len = (n_in + kSegments - 1) / kSegments;
-              seg = blockIdx.x % kSegments;
-              seg_tries = 0;
-            } else {
-              exhausted = true;
-            }
-          }
+          if (++seg_tries >= kSegments) exhausted = true;
           continue;
         }
         cur = s0 + base;
@@ -520,7 +505,7 @@ struct TraceCtl {
       const int q = ((lane - s_head) & 63) - s_count;
       if (q >= 0 && q < add) {
         const int idx = cur + q;
-        s_ray = A.in_queue ? A.in_queue[back ? long_slot(idx, A.n) : queue_slot(idx, n_in)] : idx;
+        s_ray = A.in_queue ? A.in_queue[idx] : idx;
         s_ox = A.o[3 * s_ray + 0];
         s_oy = A.o[3 * s_ray + 1];
         s_oz = A.o[3 * s_ray + 2];
@@ -543,27 +528,25 @@ struct TraceCtl {
     }
   }
 
-  // Rays that left the level (to the next level or the normal pass): slow
-  // ones (at least long_steps evaluations here) to the back region.
+  // Rays that left the level (to the next level or the normal pass), with
+  // their order keys when the next level's queue is sorted.
   __device__ inline void push(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int lane, bool done, int ray, int k) {
-    if (!A.out_queue || !__ballot(done)) return;
-    const bool slow = A.out_count_long && k >= A.long_steps;
-    const unsigned long long pm = __ballot(done && !slow), pl = __ballot(done && slow);
-    const unsigned long long below = (1ull << lane) - 1ull;
-    if (pm) {
-      pr.add(sm.ring[0], pm, done && !slow, __popcll(pm & below), ray);
-      if (pr.n >= kPushBatch) pr.publish(sm.ring[0], lane, A.out_count, A.out_queue, A.n, false, false);
-    }
-    if (pl) {
-      pr_l.add(sm.ring[1], pl, done && slow, __popcll(pl & below), ray);
-      if (pr_l.n >= kPushBatch) pr_l.publish(sm.ring[1], lane, A.out_count_long, A.out_queue, A.n, true, false);
-    }
+    if (!A.out_queue) return;
+    const unsigned long long pm = __ballot(done);
+    if (!pm) return;
+    uint8_t* rk = A.out_key ? sm.ring_key : nullptr;
+    pr.add(sm.ring, rk, pm, done, __popcll(pm & ((1ull << lane) - 1ull)), ray, order_key(k));
+    if (pr.n >= kPushBatch) pr.publish(sm.ring, rk, lane, A.out_count, A.out_queue, A.out_key, sm.hist, false);
   }
 
   __device__ inline void flush(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int lane) {
     if (!A.out_queue) return;
-    if (pr.n > 0) pr.publish(sm.ring[0], lane, A.out_count, A.out_queue, A.n, false, true);
-    if (pr_l.n > 0) pr_l.publish(sm.ring[1], lane, A.out_count_long, A.out_queue, A.n, true, true);
+    uint8_t* rk = A.out_key ? sm.ring_key : nullptr;
+    if (pr.n > 0) pr.publish(sm.ring, rk, lane, A.out_count, A.out_queue, A.out_key, sm.hist, true);
+    if (A.out_key) {
+      const int c = sm.hist[lane];
+      if (c) atomicAdd(A.out_hist + lane, c);
+    }
   }
 
   // Stage s (s = -1: prologue): finish tile s-4, refill its group, write tile s+1.
@@ -748,7 +731,7 @@ template <int P, bool RED, bool TEAM2>
 __device__ inline void trace_body(PipeSmem<kTraceCols>& sm, const TraceLevelArgs& A, int wave, int lane) {
   if (!TEAM2 && wave == 0 && NNM_WS_CTL_NOH1) {
     TraceCtl ctl;
-    ctl.init(A);
+    ctl.init(sm, A, lane);
     ctl.top_up(A, lane);
     __syncthreads();
     ctl.step(sm, A, -1, lane);
@@ -767,7 +750,7 @@ __device__ inline void trace_body(PipeSmem<kTraceCols>& sm, const TraceLevelArgs
   const bool ctl_wave = !TEAM2 && wave == 0;
   TraceCtl ctl;
   if (ctl_wave) {
-    ctl.init(A);
+    ctl.init(sm, A, lane);
     ctl.top_up(A, lane);
   }
   __syncthreads();
