@@ -11,7 +11,11 @@ Prints progress on stderr and ONE JSON line on stdout with the rays/s, the
 roofline of the dominant kernel (HIP events around each launch, algorithmic
 hidden-layer FLOPs from the per-level step counts), the error statistics
 against the FP64 CPU oracle on a row sample, and the oracle's own rate on that
-sample (cpu_baseline).
+sample (cpu_baseline).  Each form runs its K timed calls three times: back to
+back under the wall clock (the rays/s), with HIP events around each call (the
+per-call spread), and with the library's profiler (the per-kernel durations;
+its event pair around every launch adds about 10 us per kernel boundary, so
+that pass is not the throughput).
 """
 
 import argparse
@@ -72,25 +76,37 @@ def run_form(scene, precision, o, v, t, steps, warmup, final_level=-1, normal_le
     log(f"[{precision}] warmup done ({warmup} steps, final level {final_level}, normal level {normal_level})")
     timed = nnm.TraceParams(scene.step_scale, scene.eps, scene.far, scene.max_steps, final_level, normal_level,
                             profiler=prof)
-    # per-call HIP events on the calls' (current) stream, plus the wall clock around all K calls
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    # 1. the throughput: K calls back to back, wall clock around all of them
+    #    (no event between the kernels: an event pair around every launch, as
+    #    the profiler records, costs about 10 us per kernel boundary)
     t0 = time.perf_counter()
     for i in range(steps):
-        evs[i][0].record()
-        call(timed)
-        evs[i][1].record()
+        call(params)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / steps
+    # 2. the spread: HIP events around each of K more calls on their (current) stream
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for i in range(steps):
+        evs[i][0].record()
+        call(params)
+        evs[i][1].record()
+    # 3. the per-kernel durations: K more calls with the library's profiler
+    #    (HIP events around every launch, on the launch stream)
+    tp0 = time.perf_counter()
+    for i in range(steps):
+        call(timed)
+    torch.cuda.synchronize()
+    ms_prof = (time.perf_counter() - tp0) * 1e3 / steps
     per_call = sorted(a.elapsed_time(b) for a, b in evs)
     timing = {"median_ms": round(per_call[len(per_call) // 2], 4), "min_ms": round(per_call[0], 4),
               "p90_ms": round(per_call[min(len(per_call) - 1, int(0.9 * len(per_call)))], 4),
-              "load_ms": round(load_ms, 3)}
+              "profiled_ms_per_step": round(ms_prof, 4), "load_ms": round(load_ms, 3)}
     report = prof.report()
     tag = precision if final_level < 0 else f"{precision} NNM {final_level}->{normal_level}"
     log(f"[{tag}] {steps} steps: {ms:.3f} ms/step, {n / ms * 1e3 / 1e9:.3f} Grays/s; per call median "
         f"{timing['median_ms']:.3f} min {timing['min_ms']:.3f} p90 {timing['p90_ms']:.3f} ms; "
-        f"stack load {load_ms:.1f} ms")
+        f"with per-kernel events {ms_prof:.3f} ms/step; stack load {load_ms:.1f} ms")
     evals = out["steps"].to(torch.int64).sum(dim=0).cpu().tolist()
     entering = (out["steps"] > 0).to(torch.int64).sum(dim=0).cpu().tolist()
     hits = int(out["hit"].to(torch.int64).sum().item())
