@@ -312,6 +312,23 @@ static int pack_level(const nnm_level_desc& L, int precision, int device, nnm_st
         (void)ncol0;
         a0[a0_index(ks, mb, lane, MB)] = (float)(v / kTwoPiD);
       }
+  // Largest input inf-norm X with |W_0 x + b_0| <= 63 revolutions in every
+  // row (the tangent columns add a quarter revolution; the hardware sine is
+  // accurate to 64): X = min over rows of (63 - |b_r|) / sum_k |W_0[r][k]| (in
+  // revolutions, with a 1e-3 relative margin); -1 when a bias alone exceeds it.
+  double l0_safe = 1e30;
+  for (int row = 0; row < H; ++row) {
+    double a = 0.0;
+    for (int k = 0; k < L.d_in; ++k) a += std::fabs((double)W0[(size_t)row * L.d_in + k]);
+    const double b = std::fabs((double)b0[row]) / kTwoPiD;
+    a /= kTwoPiD;
+    if (b >= 63.0) {
+      l0_safe = -1.0;
+      break;
+    }
+    if (a > 0.0) l0_safe = std::min(l0_safe, (63.0 - b) / a);
+  }
+  if (l0_safe > 0.0) l0_safe = std::min(l0_safe * (1.0 - 1e-3), 1e30);
   double hidden_arg = 0.0;  // bound of |hidden pre-activation| in revolutions
   for (int layer = 1; layer < K; ++layer) {
     layer_offsets(L.d_in, H, K, layer, &wo, &bo);
@@ -445,6 +462,7 @@ static int pack_level(const nnm_level_desc& L, int precision, int device, nnm_st
   D.n_sine = K;
   D.follow_center = out->follow_center;
   D.reduce_hidden = hidden_arg > 64.0 ? 1 : 0;
+  D.l0_safe = (float)l0_safe;
   if (ws) {
     D.ws_a0 = (const float*)(base + off_ws_a0);
     D.ws_ah = (const void*)(base + off_ws_ah);
@@ -1197,6 +1215,7 @@ int fit_backward_impl(const nnm_net_shape& sh, const float* params, int device, 
   D.width = H;
   D.n_sine = K;
   D.reduce_hidden = 1;
+  D.l0_safe = -1.f;
   a.aht = pk.aht;
   a.w0t = pk.w0t;
   a.n = (int)n;
@@ -1345,6 +1364,7 @@ int siren_forward_tangent(const nnm_net_shape* shape, const float* params, int64
     D.width = shape->width;
     D.n_sine = shape->n_sine;
     D.reduce_hidden = 1;
+    D.l0_safe = -1.f;
     a.x = x;
     a.t = nullptr;
     a.value = value;

@@ -76,6 +76,8 @@ struct DevLevel {
   int n_sine;
   int follow_center;
   int reduce_hidden;  // 1: reduce hidden sine arguments with fract first
+  float l0_safe;      // inputs with inf-norm <= l0_safe keep every layer-0 sine argument
+                      // within 63 revolutions (no reduction); < 0: always reduce
   // Weight-stationary layout (width 256, two hidden layers, bf16/fp16), or null:
   const float* ws_a0;     // [4 waves][2 row blocks][3 k-steps][64 lanes] layer-0 A / 2pi
   const void* ws_ah;      // [2 layers][4 waves][2 row blocks][16 k-steps][64 lanes] 16-byte A fragments

@@ -93,6 +93,13 @@ __device__ inline float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
 __device__ inline float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }
 __device__ inline float fract_rev(float r) { return __builtin_amdgcn_fractf(r); }
 
+// v of lane l plus v of lane l ^ 32, the same sum (lower half first) on both
+// halves: one v_permlane32_swap exchanges the halves.
+__device__ inline float half_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 // Value of lane 4*(l/4)+SEL broadcast to the four lanes of each quad.
 template <int SEL>
 __device__ inline float quad_bcast(float v) {
@@ -233,10 +240,14 @@ struct SirenTile {
     }
   }
 
+  // The first layer's sine arguments need the reduction to [0, 1) revolutions
+  // unless every column's input is within L.l0_safe (inf-norm), the bound
+  // below which they stay within 63 revolutions (checked per wave).
   __device__ inline void first_layer(const NetSmem<H>* sm, const DevLevel& L, float4 in, int c) {
     f32x16_t acc[MB];
     layer0_acc(sm, L, in, c, acc);
-    activate(acc, c, true);
+    const float m = fmaxf(fmaxf(fabsf(in.x), fabsf(in.y)), fmaxf(fabsf(in.z), L.d_in == 4 ? fabsf(in.w) : 0.f));
+    activate(acc, c, !__all(m <= L.l0_safe));
   }
 
   // Hidden-layer accumulators W_i act / 2 pi + b_i / 2 pi (bias on primal columns).
@@ -312,7 +323,7 @@ struct SirenTile {
       for (int r = 0; r < 16; ++r) part = fmaf(sm->wk[acc_slot(mb, g, r)], act[mb][r], part);
       __builtin_amdgcn_sched_barrier(0);
     }
-    part += __shfl_xor(part, 32);
+    part = half_sum(part);
     if (!TAN || c == 0) part += L.bk_dev ? *L.bk_dev : L.bk;
     return part;
   }

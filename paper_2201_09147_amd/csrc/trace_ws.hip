@@ -307,7 +307,7 @@ __device__ inline float pipe_dot(const f32x16_t (&acc)[2], const float* wk, int 
       s[3] = fmaf(w.w, pipe_act<TAN, RED>(acc[rb][4 * b4 + 3], pl), s[3]);
     }
   const float t = (s[0] + s[1]) + (s[2] + s[3]);
-  return t + __shfl_xor(t, 32);
+  return half_sum(t);
 }  // (one 32-column block; callers loop over the tile's blocks)
 
 template <int C>
