@@ -11,7 +11,9 @@ Prints progress on stderr and ONE JSON line on stdout with the rays/s, the
 roofline of the dominant kernel (HIP events around each launch, algorithmic
 hidden-layer FLOPs from the per-level step counts), the error statistics
 against the FP64 CPU oracle on a row sample, and the oracle's own rate on that
-sample (cpu_baseline).  Each form runs its K timed calls three times: back to
+sample (cpu_baseline).  After its W warm-up calls each form keeps calling,
+untimed, for 0.2 s (the GPU clock ramps up over tens of milliseconds after the
+idle spell of packing a stack).  Each form runs its K timed calls three times: back to
 back under the wall clock (the rays/s), with HIP events around each call (the
 per-call spread), and with the library's profiler (the per-kernel durations;
 its event pair around every launch adds about 10 us per kernel boundary, so
@@ -30,6 +32,7 @@ if ROOT not in sys.path:
 
 METRIC = "rays/s to hit+normal at 1080p, 3-level SIREN; FP32 vs BF16-MFMA at stated err"
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}  # dense MFMA, MI355X
+SETTLE_S = 0.2  # untimed calls after the W warm-up steps, until the GPU clock has settled
 
 
 def log(msg):
@@ -73,7 +76,21 @@ def run_form(scene, precision, o, v, t, steps, warmup, final_level=-1, normal_le
     for _ in range(warmup):
         call(params)
     torch.cuda.synchronize()
-    log(f"[{precision}] warmup done ({warmup} steps, final level {final_level}, normal level {normal_level})")
+    # The GPU clock ramps up over tens of milliseconds of work after an idle
+    # spell (stack packing, the previous form's host work): keep calling,
+    # untimed, until the warm-up has run for SETTLE_S, so the K timed calls
+    # measure the settled clock (on the 1080p frame the first ~15 calls after
+    # idle take 2.0 -> 1.76 ms).
+    settle = 0
+    s0 = time.perf_counter()
+    while time.perf_counter() - s0 < SETTLE_S and settle < 1000:
+        call(params)
+        settle += 1
+        if settle % 8 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    log(f"[{precision}] warmup done ({warmup} steps + {settle} settling calls, final level {final_level}, "
+        f"normal level {normal_level})")
     timed = nnm.TraceParams(scene.step_scale, scene.eps, scene.far, scene.max_steps, final_level, normal_level,
                             profiler=prof)
     # 1. the throughput: K calls back to back, wall clock around all of them
@@ -101,7 +118,8 @@ def run_form(scene, precision, o, v, t, steps, warmup, final_level=-1, normal_le
     per_call = sorted(a.elapsed_time(b) for a, b in evs)
     timing = {"median_ms": round(per_call[len(per_call) // 2], 4), "min_ms": round(per_call[0], 4),
               "p90_ms": round(per_call[min(len(per_call) - 1, int(0.9 * len(per_call)))], 4),
-              "profiled_ms_per_step": round(ms_prof, 4), "load_ms": round(load_ms, 3)}
+              "profiled_ms_per_step": round(ms_prof, 4), "load_ms": round(load_ms, 3),
+              "settling_calls": settle}
     report = prof.report()
     tag = precision if final_level < 0 else f"{precision} NNM {final_level}->{normal_level}"
     log(f"[{tag}] {steps} steps: {ms:.3f} ms/step, {n / ms * 1e3 / 1e9:.3f} Grays/s; per call median "

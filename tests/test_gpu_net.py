@@ -90,6 +90,41 @@ def test_net_value_and_gradient(name, level, precision):
     assert ev <= tol and eg <= tol
 
 
+def _first_layer_bound(net):
+    """Input inf-norm below which every first-layer sine argument stays within
+    63 revolutions (the bound the packer derives; 1e-3 margin)."""
+    W0, b0 = (np.asarray(a, np.float64) for a in net.layers[0])
+    a = np.abs(W0).sum(axis=1) / (2 * np.pi)
+    b = np.abs(b0) / (2 * np.pi)
+    return float(np.min((63.0 - b) / a)) * (1.0 - 1e-3)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_first_layer_reduction_on_both_sides_of_the_bound(level, precision):
+    """The streaming tiles skip the first layer's reduction to [0, 1)
+    revolutions when every column of a wave lies within the level's bound.
+    Points well inside it, far outside it (arguments up to about 190
+    revolutions), and waves that mix the two, against the oracle."""
+    scene = ni.make_scene("stack3_512sq")
+    net = scene.levels[level].net
+    bound = _first_layer_bound(net)
+    rng = np.random.default_rng(90 + level)
+    n = 2048
+    inside = rng.uniform(-0.9 * bound, 0.9 * bound, size=(n, 3))
+    outside = rng.uniform(-3.0 * bound, 3.0 * bound, size=(n, 3))
+    outside[:, 0] = np.where(np.abs(outside[:, 0]) < 1.2 * bound, 1.2 * bound, outside[:, 0])
+    mixed = np.where((np.arange(n) % 7 == 3)[:, None], outside, inside)  # a few large points per wave
+    for name, x, extra in (("inside", inside, 0.0), ("outside", outside, BIGARG_EXTRA),
+                           ("mixed", mixed, BIGARG_EXTRA)):
+        x = np.ascontiguousarray(x.astype(np.float32))
+        val, grad = _net_eval_gpu(scene, level, x, None, precision)
+        rv, rg = orc.net_eval(net, x.astype(np.float64))
+        ev, eg = rel_l2(val, rv), rel_l2(grad, rg)
+        print(f"level {level} {precision} {name} (bound {bound:.2f}): rel L2 N {ev:.2e} grad {eg:.2e}")
+        assert ev <= NET_REL_L2[precision] + extra and eg <= NET_REL_L2[precision] + extra
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_scene_function_and_raw_gradient(precision):
     scene = ni.make_scene("stack3_512sq")
