@@ -30,6 +30,36 @@ __device__ inline void center_at(const DevBase& B, float t, float& cx, float& cy
   }
 }
 
+// One step of Algorithm 1 at one level for a live ray, given d = f_j - delta_j
+// at its current point: counts the evaluation, flags d < 0, advances tau by
+// step_scale d and decides the outcome: 0 keep stepping, 1 leave the level
+// (d <= eps; in fixed-iteration mode after exactly fixed_iters steps, the
+// final level only if |d| <= eps), 2 miss (non-finite d, tau beyond far, or
+// the level's budget used).  Written with selects, not branches: every lane
+// runs the same instructions.
+__device__ inline int alg1_step(const TraceLevelArgs& A, float d, float& tau, int& k, int& st) {
+  ++k;
+  const bool fin = isfinite(d);
+  const float tn = fmaf(A.step_scale, d, tau);
+  const bool far_ = fin && tn > A.far;
+  bool leave, budget;
+  if (A.fixed_iters > 0) {  // (uniform)
+    const bool end = k >= A.fixed_iters;
+    const bool final_miss = A.is_final && fabsf(d) > A.eps;
+    leave = end && !final_miss;
+    budget = end && final_miss;
+  } else {
+    leave = d <= A.eps;
+    budget = !leave && k >= A.max_steps;
+  }
+  leave = leave && fin && !far_;
+  budget = budget && fin && !far_;
+  st |= (fin ? 0 : ST_NONFINITE) | ((fin && d < 0.f) ? ST_NEG_STEP : 0) | (far_ ? ST_FAR : 0) |
+        (budget ? ST_BUDGET : 0);
+  tau = fin ? tn : tau;
+  return (!fin || far_ || budget) ? 2 : (leave ? 1 : 0);
+}
+
 // A level's input queue is popped from kSegments segments at once.  Sorted
 // input is laid out in runs of kOrderRun consecutive ranks dealt round-robin
 // to the segments (run c to segment c mod kSegments), so every segment starts

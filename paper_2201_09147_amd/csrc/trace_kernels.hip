@@ -136,35 +136,7 @@ k_trace_level(TraceLevelArgs A) {
         base_term = base_radius(dx, dy, z) - A.B.r0;
       }
       const float f = fmaf(A.L.amplitude, N, base_term);
-      const float d = f - A.delta;
-      ++k;
-      if (!isfinite(d)) {
-        st |= ST_NONFINITE;
-        outcome = 2;
-      } else {
-        if (d < 0.f) st |= ST_NEG_STEP;
-        tau = fmaf(A.step_scale, d, tau);
-        if (tau > A.far) {
-          st |= ST_FAR;
-          outcome = 2;
-        } else if (A.fixed_iters > 0) {
-          // fixed-iteration mode: leave the level after exactly fixed_iters steps;
-          // the final level hits iff its last |d| <= eps
-          if (k >= A.fixed_iters) {
-            if (A.is_final && fabsf(d) > A.eps) {
-              st |= ST_BUDGET;
-              outcome = 2;
-            } else {
-              outcome = 1;
-            }
-          }
-        } else if (d <= A.eps) {
-          outcome = 1;
-        } else if (k >= A.max_steps) {
-          st |= ST_BUDGET;
-          outcome = 2;
-        }
-      }
+      outcome = alg1_step(A, f - A.delta, tau, k, st);
     }
     // Compaction: rays that finished the level enter the wave's push ring
     // (both halves of a column hold the same slot: the lower half's ballot).

@@ -585,35 +585,7 @@ struct TraceCtl {
         base_term = base_radius(dx, dy, z) - A.B.r0;
       }
       const float f = fmaf(L.amplitude, N, base_term);
-      const float d = f - A.delta;
-      ++k;
-      if (!isfinite(d)) {
-        st |= ST_NONFINITE;
-        outcome = 2;
-      } else {
-        if (d < 0.f) st |= ST_NEG_STEP;
-        tau = fmaf(A.step_scale, d, tau);
-        if (tau > A.far) {
-          st |= ST_FAR;
-          outcome = 2;
-        } else if (A.fixed_iters > 0) {
-          // fixed-iteration mode: leave the level after exactly fixed_iters steps;
-          // the final level hits iff its last |d| <= eps
-          if (k >= A.fixed_iters) {
-            if (A.is_final && fabsf(d) > A.eps) {
-              st |= ST_BUDGET;
-              outcome = 2;
-            } else {
-              outcome = 1;
-            }
-          }
-        } else if (d <= A.eps) {
-          outcome = 1;
-        } else if (k >= A.max_steps) {
-          st |= ST_BUDGET;
-          outcome = 2;
-        }
-      }
+      outcome = alg1_step(A, f - A.delta, tau, k, st);
     }
     push(sm, A, lane, outcome == 1, ray, k);
     if (outcome != 0) {
