@@ -143,6 +143,13 @@ def make_scene(name: str) -> Scene:
         levels = [SceneLevel(siren_init(31, 3, 64, 2, 0.015), 0.015, 0.05),
                   SceneLevel(siren_init(32, 3, 128, 3, 0.02), 0.02, 0.0)]
         return Scene(name, levels, 512, 512)
+    if name == "stack3_wsmid_512sq":
+        # a (256,2) level in the middle of the stack: the weight-stationary
+        # tracer as a non-final level (its queue sorted for the next level)
+        levels = [SceneLevel(siren_init(2, 3, 64, 2, 0.015), 0.015, 0.05),
+                  SceneLevel(siren_init(3, 3, 256, 3, 0.02), 0.02, 0.01),
+                  SceneLevel(siren_init(23, 3, 256, 4, 0.02), 0.02, 0.0)]
+        return Scene(name, levels, 512, 512)
     if name == "stack3_bigarg_512sq":
         levels = _stack3()
         levels[2] = SceneLevel(siren_init(3, 3, 256, 3, 0.02, bias_turns=300), 0.02, 0.0)
@@ -162,4 +169,4 @@ def make_scene(name: str) -> Scene:
 
 
 WORKLOADS = ["single_64x1_128sq", "stack3_512sq", "stack3_1080p", "stack3_4096sq",
-             "stack2_64x1_128x2_512sq", "stack3_bigarg_512sq", "anim16_1024sq", "fit_torus_256x2"] + list(TABLE3_ROWS)
+             "stack2_64x1_128x2_512sq", "stack3_bigarg_512sq", "stack3_wsmid_512sq", "anim16_1024sq", "fit_torus_256x2"] + list(TABLE3_ROWS)

@@ -414,13 +414,16 @@ def test_table3_rows_fixed_iterations(row, precision):
                                             ("table3_64x1_256x1", "fp32"), ("table3_64x1_256x1", "bf16"),
                                             ("table3_64x1_256x3", "fp32"), ("table3_64x1_256x3", "bf16"),
                                             ("stack3_bigarg_512sq", "fp32"), ("stack3_bigarg_512sq", "bf16"),
-                                            ("stack3_bigarg_512sq", "fp16")])
+                                            ("stack3_bigarg_512sq", "fp16"),
+                                            ("stack3_wsmid_512sq", "fp32"), ("stack3_wsmid_512sq", "bf16")])
 def test_other_widths_and_depths_eps_mode(name, precision):
     """Eps-terminated multiscale tracing with normals for the configurations the
     validator accepts beyond the headline stack: width 128, (256,1) and (256,3)
-    fine levels (streaming tile in every form), and a (256,2) level whose hidden
+    fine levels (streaming tile in every form), a (256,2) level whose hidden
     sine arguments reach 300 revolutions (the range-reduced streaming tile in
-    fp32, the range-reduced weight-stationary kernels in bf16 / fp16)."""
+    fp32, the range-reduced weight-stationary kernels in bf16 / fp16), and a
+    (256,2) level in the middle of the stack (in bf16 the weight-stationary
+    tracer pushes its rays, with their order keys, to a (256,3) level)."""
     s = ni.make_scene(name).with_size(192, 160)
     o, v, _ = s.rays()
     for final, normal in ((len(s.levels) - 1, len(s.levels) - 1), (len(s.levels) - 2, len(s.levels) - 1)):
