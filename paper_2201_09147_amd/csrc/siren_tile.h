@@ -149,6 +149,11 @@ __device__ inline float layer0_input(float4 in, int d_in, int c, int ks, int g) 
   return k == 3 ? 1.f : 0.f;
 }
 
+// Inf-norm of a network input (x, y, z[, t]).
+__device__ inline float input_norm(float4 in, int d_in) {
+  return fmaxf(fmaxf(fabsf(in.x), fabsf(in.y)), fmaxf(fabsf(in.z), d_in == 4 ? fabsf(in.w) : 0.f));
+}
+
 // acc += A b over an H x H layer with 32x32x2 fp32 MFMAs: k-step ks uses
 // b[ks/16][ks%16] (accumulator layout of the previous layer); A packed as
 // f32x4 groups of four k-steps, streamed through a register ring.
@@ -246,8 +251,7 @@ struct SirenTile {
   __device__ inline void first_layer(const NetSmem<H>* sm, const DevLevel& L, float4 in, int c) {
     f32x16_t acc[MB];
     layer0_acc(sm, L, in, c, acc);
-    const float m = fmaxf(fmaxf(fabsf(in.x), fabsf(in.y)), fmaxf(fabsf(in.z), L.d_in == 4 ? fabsf(in.w) : 0.f));
-    activate(acc, c, !__all(m <= L.l0_safe));
+    activate(acc, c, !__all(input_norm(in, L.d_in) <= L.l0_safe));
   }
 
   // Hidden-layer accumulators W_i act / 2 pi + b_i / 2 pi (bias on primal columns).
@@ -311,9 +315,9 @@ struct SirenTile {
     activate(acc, c, L.reduce_hidden != 0);
   }
 
-  // Output layer on the current activations: per lane, the reduced value of
-  // its column (N for primal columns, dN/dx_{c-1} for tangent columns).
-  __device__ inline float output(const NetSmem<H>* sm, const DevLevel& L, int c) {
+  // Output layer, this lane's half: the dot of W_K with the 16 MB rows the
+  // lane holds (the column's other rows sit in lane l ^ 32).
+  __device__ inline float output_part(const NetSmem<H>* sm) {
     const int g = (threadIdx.x & 63) >> 5;
     NNM_MEM_FENCE();
     float part = 0.f;
@@ -323,7 +327,13 @@ struct SirenTile {
       for (int r = 0; r < 16; ++r) part = fmaf(sm->wk[acc_slot(mb, g, r)], act[mb][r], part);
       __builtin_amdgcn_sched_barrier(0);
     }
-    part = half_sum(part);
+    return part;
+  }
+
+  // Output layer on the current activations: per lane, the reduced value of
+  // its column (N for primal columns, dN/dx_{c-1} for tangent columns).
+  __device__ inline float output(const NetSmem<H>* sm, const DevLevel& L, int c) {
+    float part = half_sum(output_part(sm));
     if (!TAN || c == 0) part += L.bk_dev ? *L.bk_dev : L.bk;
     return part;
   }
@@ -338,5 +348,58 @@ struct SirenTile {
     return output(sm, L, c);
   }
 };
+
+// Two forward tiles of one wave evaluated layer by layer side by side, so the
+// MFMAs of one overlap the other's sines: tile 0's column n is the point in0
+// of lane n, tile 1's column n the point in1 of lane n (both inputs the same
+// on the two halves).  Returns, per lane l, N of column l % 32 of tile l / 32:
+// with in0 / in1 taken from lanes n / n + 32, every lane gets the value at its
+// own point.  Each column's value is computed as by SirenTile::eval (same
+// operations, same order), apart from the first layer's reduction, which here
+// is decided over both tiles.
+template <int H, int P>
+struct SirenPair {
+  static constexpr int MB = H / 32;
+  SirenTile<H, P, false> t0, t1;
+
+  __device__ inline void activate(const f32x16_t* a0, const f32x16_t* a1, bool reduce) {
+    if (reduce) {
+      t0.template activate_r<true>(a0, 0);
+      t1.template activate_r<true>(a1, 0);
+    } else {
+      t0.template activate_r<false>(a0, 0);
+      t1.template activate_r<false>(a1, 0);
+    }
+  }
+
+  __device__ inline float eval(const NetSmem<H>* sm, const DevLevel& L, float4 in0, float4 in1) {
+    NNM_MEM_FENCE();
+    f32x16_t a0[MB], a1[MB];
+    t0.layer0_acc(sm, L, in0, 0, a0);
+    t1.layer0_acc(sm, L, in1, 0, a1);
+    activate(a0, a1, !__all(fmaxf(input_norm(in0, L.d_in), input_norm(in1, L.d_in)) <= L.l0_safe));
+    for (int layer = 1; layer < L.n_sine; ++layer) {
+      t0.hidden_acc(sm, L, layer, 0, a0);
+      t1.hidden_acc(sm, L, layer, 0, a1);
+      activate(a0, a1, L.reduce_hidden != 0);
+    }
+    // One v_permlane32_swap pairs the halves: the first result holds tile 0's
+    // lower-half partials then tile 1's, the second the upper halves'.
+    const float p0 = t0.output_part(sm), p1 = t1.output_part(sm);
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(p0), __float_as_uint(p1), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]) + (L.bk_dev ? *L.bk_dev : L.bk);
+  }
+};
+
+// Value of lane l % 32 (LO) or of lane 32 + l % 32 (!LO) on every lane.
+template <bool LO>
+__device__ inline float half_bcast(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(LO ? r[0] : r[1]);
+}
+template <bool LO>
+__device__ inline float4 half_bcast4(float4 v) {
+  return make_float4(half_bcast<LO>(v.x), half_bcast<LO>(v.y), half_bcast<LO>(v.z), half_bcast<LO>(v.w));
+}
 
 }  // namespace nnm

@@ -2,8 +2,9 @@
 // evaluation kernels for gfx950.
 //
 // Multiscale sphere tracing (Algorithm 1 of the paper) runs one persistent
-// kernel per level.  Each wavefront owns 32 ray slots (one tile column each) and
-// loops: refill empty slots from the level's input queue (one atomic per wave),
+// kernel per level.  Each wavefront owns 32 ray slots (one tile column each,
+// held by both lane halves) or, for narrow nets, 64 (one per lane, evaluated as
+// two tiles side by side, which halves the per-ray control work) and loops: refill empty slots from the level's input queue (one atomic per wave),
 // evaluate f_j at all slots with the fused SIREN tile, step every live ray
 // (tau += s d with d = f_j - delta_j), and retire rays that left the level: to
 // the next level's queue (d <= eps), to the hit queue (last level), or as a miss
@@ -31,11 +32,27 @@ __global__ void k_zero_ints(int* p, int count) {
 #ifndef NNM_TRACE_WAVES_64
 #define NNM_TRACE_WAVES_64 1
 #endif
-template <int H>
-constexpr int trace_waves_per_eu() { return H == 32 ? NNM_TRACE_WAVES_32 : (H == 64 ? NNM_TRACE_WAVES_64 : 1); }
+// Widths traced with one ray per lane (two tiles per wave; bf16 and fp16
+// only: with fp32 hidden layers the matrix pipe sets the pace and the pairing
+// gains nothing), and their waves per SIMD.
+#ifndef NNM_TRACE_PAIR_MAX_H
+#define NNM_TRACE_PAIR_MAX_H 64
+#endif
+#ifndef NNM_TRACE_PAIR_WAVES_32
+#define NNM_TRACE_PAIR_WAVES_32 4
+#endif
+#ifndef NNM_TRACE_PAIR_WAVES_64
+#define NNM_TRACE_PAIR_WAVES_64 2
+#endif
+constexpr bool trace_pair(int H, int P) { return P != PREC_FP32 && H <= NNM_TRACE_PAIR_MAX_H; }
+template <int H, bool PAIR>
+constexpr int trace_waves_per_eu() {
+  return PAIR ? (H == 32 ? NNM_TRACE_PAIR_WAVES_32 : NNM_TRACE_PAIR_WAVES_64)
+              : (H == 32 ? NNM_TRACE_WAVES_32 : (H == 64 ? NNM_TRACE_WAVES_64 : 1));
+}
 
-template <int H, int P>
-__global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(trace_waves_per_eu<H>())))
+template <int H, int P, bool PAIR>
+__global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(trace_waves_per_eu<H, PAIR>())))
 k_trace_level(TraceLevelArgs A) {
   __shared__ NetSmem<H> sm;
   // Per-wave ring of rays that finished the level, flushed to the output queue
@@ -49,10 +66,18 @@ k_trace_level(TraceLevelArgs A) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 31;
   const int g = lane >> 5;
+  // The lane's ray slot: its own (PAIR) or its tile column's, whose state
+  // both halves hold and whose results the lower half writes.  Slot masks are
+  // ballots restricted to one lane per slot.
+  constexpr int kSlots = PAIR ? 64 : 32;
+  const bool writer = PAIR || g == 0;
+  const unsigned long long slot_lanes = PAIR ? ~0ull : 0xffffffffull;
+  const unsigned long long below = (1ull << (PAIR ? lane : col)) - 1ull;
   int* ring = push_ring[threadIdx.x >> 6];
   uint8_t* ring_key = A.out_key ? push_key[threadIdx.x >> 6] : nullptr;
   const int n_in = A.in_count ? *A.in_count : A.n;
   SirenTile<H, P, false> tile;
+  SirenPair<H, P> pair;
   int ray = -1, k = 0, st = 0;
   float tau = 0.f, ox = 0.f, oy = 0.f, oz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, tt = 0.f, cx = 0.f, cy = 0.f;
   // Wave-uniform work chunk [cur, end) of the input queue and push-ring state.
@@ -65,14 +90,13 @@ k_trace_level(TraceLevelArgs A) {
   PushRing pr;
   const int nwaves = gridDim.x * (kBlockThreads / 64);
   const int wave_id = blockIdx.x * (kBlockThreads / 64) + (threadIdx.x >> 6);
-  const int chunk = min(kChunk, max(32, (n_in / (8 * nwaves)) & ~31));
+  const int chunk = min(kChunk, max(kSlots, (n_in / (8 * nwaves)) & ~31));
   int seg = wave_id % kSegments, seg_tries = 0;
   bool exhausted = false;
   for (;;) {
     // Refill empty slots from the wave's chunk, grabbing a new chunk of
-    // queue entries (one atomic) when it runs dry.  Both halves of a column
-    // hold the same slot state, so the lower half's ballot is enough.
-    unsigned int emask = (unsigned int)__ballot(ray < 0);
+    // queue entries (one atomic) when it runs dry.
+    unsigned long long emask = __ballot(ray < 0) & slot_lanes;
     while (emask != 0u && !exhausted) {
       if (cur >= end) {
         int s0, s_len;
@@ -93,10 +117,10 @@ k_trace_level(TraceLevelArgs A) {
         end = s0 + min(base + chunk, s_len);
       }
       const int avail = end - cur;
-      const int cnt = __popc(emask);
+      const int cnt = __popcll(emask);
       const int take = min(cnt, avail);
       if (ray < 0) {
-        const int pos = __popc(emask & ((1u << col) - 1u));
+        const int pos = __popcll(emask & below);
         if (pos < take) {
           const int idx = cur + pos;
           ray = A.in_queue ? A.in_queue[idx] : idx;
@@ -112,7 +136,7 @@ k_trace_level(TraceLevelArgs A) {
           if (A.level == 0) {
             tau = 0.f;
             st = 0;
-            if (A.steps && g == 0)
+            if (A.steps && writer)
               for (int j = 1; j < A.m; ++j) A.steps[(long long)ray * A.m + j] = 0;
           } else {
             tau = A.depth[ray];
@@ -121,12 +145,25 @@ k_trace_level(TraceLevelArgs A) {
         }
       }
       cur += take;
-      emask = (unsigned int)__ballot(ray < 0);
+      emask = __ballot(ray < 0) & slot_lanes;
     }
     if (__ballot(ray >= 0) == 0ull) break;
 
     const float x = fmaf(tau, vx, ox), y = fmaf(tau, vy, oy), z = fmaf(tau, vz, oz);
-    const float N = tile.eval(&sm, A.L, net_input(A.L, x, y, z, tt, cx, cy), 0);
+    const float4 in = net_input(A.L, x, y, z, tt, cx, cy);
+    float N;
+    if constexpr (PAIR) {
+      // Tile 0 takes the rays of lanes 0..31, tile 1 those of lanes 32..63; a
+      // half with no live ray is not evaluated.
+      const unsigned long long lv = __ballot(ray >= 0);
+      const float4 in0 = half_bcast4<true>(in), in1 = half_bcast4<false>(in);
+      if ((unsigned int)lv != 0u && (lv >> 32) != 0ull)
+        N = pair.eval(&sm, A.L, in0, in1);
+      else
+        N = tile.eval(&sm, A.L, (unsigned int)lv != 0u ? in0 : in1, 0);
+    } else {
+      N = tile.eval(&sm, A.L, in, 0);
+    }
 
     int outcome = 0;  // 0: keep stepping, 1: left the level through d <= eps, 2: miss
     if (ray >= 0) {
@@ -138,17 +175,16 @@ k_trace_level(TraceLevelArgs A) {
       const float f = fmaf(A.L.amplitude, N, base_term);
       outcome = alg1_step(A, f - A.delta, tau, k, st);
     }
-    // Compaction: rays that finished the level enter the wave's push ring
-    // (both halves of a column hold the same slot: the lower half's ballot).
+    // Compaction: rays that finished the level enter the wave's push ring.
     if (A.out_queue) {
-      const unsigned long long pm = (unsigned int)__ballot(outcome == 1);
+      const unsigned long long pm = __ballot(outcome == 1) & slot_lanes;
       if (pm) {
-        pr.add(ring, ring_key, pm, outcome == 1 && g == 0, __popcll(pm & ((1ull << col) - 1ull)), ray, order_key(k));
+        pr.add(ring, ring_key, pm, outcome == 1 && writer, __popcll(pm & below), ray, order_key(k));
         if (pr.n >= kPushBatch) pr.publish(ring, ring_key, lane, A.out_count, A.out_queue, A.out_key, key_hist, false);
       }
     }
     if (outcome != 0) {
-      if (g == 0) {
+      if (writer) {
         if (A.steps) A.steps[(long long)ray * A.m + A.level] = (uint8_t)k;
         if (outcome == 2) {
           A.depth[ray] = __builtin_inff();
@@ -370,7 +406,7 @@ hipError_t launch_queue_order(const QueueOrderArgs& a, int grid, hipStream_t s) 
 }
 
 hipError_t launch_trace_level(int width, int prec, const TraceLevelArgs& a, int grid, hipStream_t s) {
-#define CALL(H, P) hipLaunchKernelGGL((k_trace_level<H, P>), dim3(grid), dim3(kBlockThreads), 0, s, a)
+#define CALL(H, P) hipLaunchKernelGGL((k_trace_level<H, P, trace_pair(H, P)>), dim3(grid), dim3(kBlockThreads), 0, s, a)
   NNM_DISPATCH(width, prec, CALL)
 #undef CALL
   return hipGetLastError();
@@ -403,7 +439,7 @@ int resident_blocks(int width, int prec, int kind, int device) {
   int out = 0;
 #define CALL(H, P)                                                                              \
   {                                                                                             \
-    const void* fn = kind == 0 ? (const void*)k_trace_level<H, P>                               \
+    const void* fn = kind == 0 ? (const void*)k_trace_level<H, P, trace_pair(H, P)>             \
                                : (kind == 1 ? (const void*)k_normal<H, P> : (const void*)k_points<H, P>); \
     out = occupancy_of(fn, device);                                                             \
   }

@@ -236,6 +236,31 @@ def test_edge_cases():
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_paired_tiles_small_and_ragged_counts(precision):
+    """In bf16/fp16 the (32,1) and (64,1) levels trace one ray per lane, as two
+    32-column tiles per wave, and evaluate only one tile while a lane half has
+    no live ray.  Ray counts below, at and around one and two tiles, and a
+    few hundred, take the two-tile and the one-tile paths with either half
+    live; every count is compared with the oracle ray by ray (with fewer than
+    1,000 rays the mask gate means no ray may disagree)."""
+    s = ni.make_scene("stack3_512sq")
+    o, v, _ = s.rays()
+    rng = np.random.default_rng(2201)
+    stack = nnm.load_siren_stack(s, precision, 0)
+    hits = 0
+    for n in (1, 2, 31, 32, 33, 63, 64, 65, 97, 300):
+        idx = rng.choice(o.shape[0], n, replace=False)
+        oo, vv = np.ascontiguousarray(o[idx]), np.ascontiguousarray(v[idx])
+        g = gpu_trace(s, oo, vv, stack=stack)
+        r = orc.trace(s, oo, vv)
+        st = compare(g, r)
+        check_lowp(st)
+        hits += st["hits"]
+    stack.close()
+    assert hits > 100
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
 def test_weight_stationary_matches_streaming(precision):
     """The (256,2) level runs the weight-stationary kernels in bf16/fp16; the
     streaming kernels (kernels="streaming") compute the same sums in another K order."""
