@@ -632,7 +632,7 @@ struct TraceCtl {
     // refill freed slots: parked rays first, then the staging ring
     if (!parked && park_count > 0) {
       const unsigned long long fmask = __ballot(slot && ray < 0);
-      const int takep = min(__popcll(fmask), park_count);
+      const int takep = min((int)__popcll(fmask), park_count);
       const int p = __popcll(fmask & ((1ull << lane) - 1ull));
       if (slot && ray < 0 && p < takep) {
         const int e = (park_head + p) & (kTraceCols - 1);
@@ -655,7 +655,7 @@ struct TraceCtl {
       park_count -= takep;
     }
     const unsigned long long emask = __ballot(slot && ray < 0);
-    const int take = min(__popcll(emask), s_count);
+    const int take = min((int)__popcll(emask), s_count);
     const int p = __popcll(emask & ((1ull << lane) - 1ull));
     const bool fill = slot && ray < 0 && p < take;
     const int src = fill ? ((s_head + p) & 63) : lane;
