@@ -77,6 +77,26 @@ __device__ inline void segment_bounds(int seg, int n, int& start, int& len) {
   len = (full + (seg < extra ? 1 : 0)) * kOrderRun - (seg == last_seg ? short_by : 0);
 }
 
+// A segment of a level's input queue that may still hold entries: one
+// wave-wide load of all kSegments pop counters (lane s reads segment s's, past
+// the L1, since other waves move them with atomics) against each segment's
+// length, then the (pick mod count)-th of the open segments, so that waves
+// leaving drained segments spread over the open ones instead of all meeting
+// on one counter.  -1 when every counter has passed its segment's end: the
+// counters only grow, so the queue is then drained for good.  Call with all
+// 64 lanes active.
+__device__ inline int next_open_segment(int* heads, int n, int pick, int lane) {
+  static_assert(kSegments == 64, "one segment per lane");
+  int s0, len;
+  segment_bounds(lane, n, s0, len);
+  const int h = __hip_atomic_load(heads + lane * kHeadStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long open = __ballot(h < len);
+  if (open == 0ull) return -1;
+  const int k = pick % __popcll(open);
+  const bool mine = ((open >> lane) & 1ull) && __popcll(open & ((1ull << lane) - 1ull)) == k;
+  return __builtin_ctzll(__ballot(mine));
+}
+
 // Queue position of sorted rank r in that layout.
 __device__ inline int sorted_position(int r, int n) {
   const int c = r / kOrderRun;

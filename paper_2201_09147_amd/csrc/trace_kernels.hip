@@ -83,7 +83,8 @@ k_trace_level(TraceLevelArgs A) {
   // Wave-uniform work chunk [cur, end) of the input queue and push-ring state.
   // The queue is split into kSegments segments with one pop counter each
   // (separate cache lines, so the atomics spread over many addresses); a wave
-  // starts in segment (wave id mod kSegments) and moves on when it is empty.
+  // starts in segment (wave id mod kSegments) and, when it is empty, moves on
+  // to one that still holds entries (one read of all counters).
   // Chunks hold about n_in / (8 * resident waves) entries (32..kChunk), so
   // every wave takes several chunks and the queue drains evenly.
   int cur = 0, end = 0;
@@ -91,7 +92,7 @@ k_trace_level(TraceLevelArgs A) {
   const int nwaves = gridDim.x * (kBlockThreads / 64);
   const int wave_id = blockIdx.x * (kBlockThreads / 64) + (threadIdx.x >> 6);
   const int chunk = min(kChunk, max(kSlots, (n_in / (8 * nwaves)) & ~31));
-  int seg = wave_id % kSegments, seg_tries = 0;
+  int seg = wave_id % kSegments;
   bool exhausted = false;
   for (;;) {
     // Refill empty slots from the wave's chunk, grabbing a new chunk of
@@ -105,9 +106,9 @@ k_trace_level(TraceLevelArgs A) {
         if (lane == 0) base = atomicAdd(A.in_heads + seg * kHeadStride, chunk);
         base = __shfl(base, 0);
         if (base >= s_len) {
-          // this segment is drained: try the next one
-          seg = (seg + 1) % kSegments;
-          if (++seg_tries >= kSegments) {
+          // this segment is drained: on to one that is not, if any
+          seg = next_open_segment(A.in_heads, n_in, wave_id, lane);
+          if (seg < 0) {
             exhausted = true;
             break;
           }

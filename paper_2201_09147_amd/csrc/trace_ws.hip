@@ -458,7 +458,7 @@ struct TraceCtl {
   int s_ray, s_st;
   float s_ox, s_oy, s_oz, s_vx, s_vy, s_vz, s_tt, s_tau;
   int s_head, s_count;
-  int cur, end, seg, seg_tries, chunk, n_in;
+  int cur, end, seg, chunk, n_in;
   bool exhausted;
   PushRing pr;
   int glive;  // bit G: slot group G holds rays
@@ -478,7 +478,6 @@ struct TraceCtl {
 #endif
     chunk = min(kChunk, max(64, (n_in / (NNM_WS_CHUNK_DIV * (int)gridDim.x)) & ~63));
     seg = blockIdx.x % kSegments;
-    seg_tries = 0;
     exhausted = false;
     sm.hist[lane] = 0;  // (only this wave touches it)
   }
@@ -493,9 +492,9 @@ struct TraceCtl {
         if (lane == 0) base = atomicAdd(A.in_heads + seg * kHeadStride, chunk);
         base = __shfl(base, 0);
         if (base >= s_len) {
-          // this segment is drained: the next one
-          seg = (seg + 1) % kSegments;
-          if (++seg_tries >= kSegments) exhausted = true;
+          // this segment is drained: on to one that is not, if any
+          seg = next_open_segment(A.in_heads, n_in, blockIdx.x, lane);
+          if (seg < 0) exhausted = true;
           continue;
         }
         cur = s0 + base;
