@@ -3,9 +3,11 @@
 //
 // Multiscale sphere tracing (Algorithm 1 of the paper) runs one persistent
 // kernel per level.  Each wavefront owns 32 ray slots (one tile column each,
-// held by both lane halves) or, for narrow nets, 64 (one per lane, evaluated as
-// two tiles side by side, which halves the per-ray control work) and loops: refill empty slots from the level's input queue (one atomic per wave),
-// evaluate f_j at all slots with the fused SIREN tile, step every live ray
+// held by both lane halves) or, for narrow nets in bf16/fp16, 64 (one per
+// lane, evaluated as two tiles side by side, which halves the per-ray control
+// work) and loops: refill empty slots from the level's input queue (one
+// atomic per chunk of entries), evaluate f_j at all slots with the fused
+// SIREN tile, step every live ray
 // (tau += s d with d = f_j - delta_j), and retire rays that left the level: to
 // the next level's queue (d <= eps), to the hit queue (last level), or as a miss
 // (tau > far, budget used, non-finite).  Slots freed by retired rays are refilled
@@ -85,8 +87,8 @@ k_trace_level(TraceLevelArgs A) {
   // (separate cache lines, so the atomics spread over many addresses); a wave
   // starts in segment (wave id mod kSegments) and, when it is empty, moves on
   // to one that still holds entries (one read of all counters).
-  // Chunks hold about n_in / (8 * resident waves) entries (32..kChunk), so
-  // every wave takes several chunks and the queue drains evenly.
+  // Chunks hold about n_in / (8 * resident waves) entries (kSlots..kChunk),
+  // so every wave takes several chunks and the queue drains evenly.
   int cur = 0, end = 0;
   PushRing pr;
   const int nwaves = gridDim.x * (kBlockThreads / 64);
