@@ -7,10 +7,10 @@
 // lane, evaluated as two tiles side by side, which halves the per-ray control
 // work) and loops: refill empty slots from the level's input queue (one
 // atomic per chunk of entries), evaluate f_j at all slots with the fused
-// SIREN tile, step every live ray
-// (tau += s d with d = f_j - delta_j), and retire rays that left the level: to
-// the next level's queue (d <= eps), to the hit queue (last level), or as a miss
-// (tau > far, budget used, non-finite).  Slots freed by retired rays are refilled
+// SIREN tile, step every live ray (tau += s d with d = f_j - delta_j), and
+// retire rays that left the level: to the next level's queue (d <= eps), to
+// the hit queue (last level), or as a miss (tau > far, budget used,
+// non-finite).  Slots freed by retired rays are refilled
 // on the next iteration, so tiles stay dense while the queue lasts and every
 // tile evaluates one network only.  The normal pass then evaluates the normal
 // level's forward and three tangent columns (Sec. 5.1) at the hit points.
